@@ -1,0 +1,47 @@
+"""Pins of the FP64 MACE oracle (paper Sec. III): the averaging identities and
+the consensus equilibrium of proximal agents, which solves the multi-regularised
+MAP problem of eq. (map_multireg)."""
+import numpy as np
+
+import oracle
+from oracle import mace
+from paper_2008_01567_amd import synth
+
+
+def test_G_is_idempotent_and_reflection_is_involution():
+    rng = np.random.default_rng(0)
+    W = [rng.standard_normal(50) for _ in range(4)]
+    for beta in (0.3, 1.0, 2.5):
+        GW = mace.G(W, beta)
+        GGW = mace.G(GW, beta)
+        assert all(np.allclose(a, b, rtol=0, atol=1e-14) for a, b in zip(GW, GGW))
+        R = [2 * g - w for g, w in zip(GW, W)]
+        RR = [2 * g - r for g, r in zip(mace.G(R, beta), R)]
+        assert all(np.allclose(a, b, rtol=0, atol=1e-13) for a, b in zip(RR, W))
+    # beta = 1 weighs the forward model and the mean of the priors equally
+    m = mace.weighted_mean(W, 1.0)
+    assert np.allclose(m, 0.5 * W[0] + 0.5 * (W[1] + W[2] + W[3]) / 3)
+
+
+def test_ridge_agents_reach_map_solution():
+    """Proximal agents H_k(x) = x / (1 + lam sigma^2) (prox of lam/2 ||x||^2): Algorithm 1
+    converges to the solution of (A^T Lambda A + beta lam I) x = A^T Lambda y."""
+    cfg = synth.config("tiny8")
+    g = synth.make_geometry(cfg).subset([0])
+    x0 = synth.make_phantom(cfg, [0])
+    y, lw = oracle.make_measurement(cfg, g, x0, [0])
+    M = oracle.FrameMatrix(g, 0)
+    sigma, lam_r, beta, rho, K = 0.5, 3.0, 1.0, 0.5, 3
+
+    def agents(W, X):
+        xL, _ = M.prox_cg(W[0], y, lw, sigma, tol=1e-14)
+        return [xL] + [w / (1.0 + lam_r * sigma ** 2) for w in W[1:]]
+    agents.n_agents = K + 1
+
+    xs, X, W = mace.mann_partial(agents, np.zeros(M.ncols), beta, rho, 300)
+    A = M.dense()
+    want = np.linalg.solve(A.T @ (lw[:, None] * A) + beta * lam_r * np.eye(M.ncols), A.T @ (lw * y))
+    xbar = mace.weighted_mean(W, beta)
+    assert np.linalg.norm(xbar - want) <= 1e-6 * np.linalg.norm(want)
+    # at equilibrium every agent's output equals the consensus value
+    assert np.linalg.norm(xs - want) <= 1e-6 * np.linalg.norm(want)

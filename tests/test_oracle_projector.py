@@ -1,0 +1,214 @@
+"""Pins of the FP64 oracle projector (system matrix of paper eq. (LL_time_expand)).
+
+The oracle is checked against things other than itself: brute-force clipping
+of every voxel, hand-derived lengths (tests/golden), the chord through the
+volume box, analytic line integrals of ellipsoids, a 90-degree symmetry of the
+scanner and the dot-product identity of its transpose.
+"""
+import dataclasses
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_01567_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _geom(n=(8, 8, 8), det=(12, 12), rs=50.0, rsd=100.0, angles=(0.3,), du=2.0, dv=2.0, off=(0.0, 0.0)):
+    ang = np.asarray(angles, dtype=np.float64)
+    return synth.Geometry(n[0], n[1], n[2], 1, det[0], det[1], du, dv, rs, rsd,
+                          np.array([0, len(ang)], dtype=np.int64), ang, off[0], off[1])
+
+
+def _entries_dict(idx, ln, thresh=0.0):
+    return {int(i): float(l) for i, l in zip(idx, ln) if l > thresh}
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_siddon_equals_brute_force(seed):
+    """Siddon's merged crossings and per-voxel clipping give the same row (<=1e-13)."""
+    rng = np.random.default_rng(seed)
+    n = tuple(int(v) for v in rng.integers(3, 11, size=3))
+    g = _geom(n=n, det=(7, 5), rs=rng.uniform(20, 60), rsd=rng.uniform(60, 120),
+              angles=rng.uniform(0, 2 * math.pi, size=3), du=rng.uniform(0.5, 3), dv=rng.uniform(0.5, 3),
+              off=tuple(rng.uniform(-1, 1, size=2)))
+    for view in range(3):
+        for iv in range(g.nv):
+            for iu in range(g.nu):
+                S, D = oracle.ray(g, g.angles[view], iu, iv)
+                a = _entries_dict(*oracle.ray_entries(g, S, D, "siddon"), 1e-13)
+                b = _entries_dict(*oracle.ray_entries(g, S, D, "brute"), 1e-13)
+                assert a.keys() == b.keys()
+                for k in a:
+                    assert abs(a[k] - b[k]) <= 1e-13
+
+
+def test_csr_siddon_equals_brute_tiny16():
+    cfg = synth.config("tiny16")
+    g = synth.make_geometry(cfg)
+    A = oracle.FrameMatrix(g, 0, "siddon").dense()
+    B = oracle.FrameMatrix(g, 0, "brute").dense()
+    assert np.abs(A - B).max() <= 1e-13
+    assert (A > 0).sum() > 1000
+
+
+def test_golden_tie_rule():
+    """Hand-derived lengths, including rays lying in voxel faces (half-open rule)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "ties_2x2x2.txt")) if l.strip() and not l.startswith("#")]
+    cases = {}
+    for c, th, ou, ov, vox, ln in rows:
+        cases.setdefault((c, float(th), float(ou), float(ov)), {})[int(vox)] = float(ln)
+    for (c, th, ou, ov), want in cases.items():
+        g = _geom(n=(2, 2, 2), det=(1, 1), rs=10.0, rsd=20.0, angles=(th,), off=(ou, ov))
+        S, D = oracle.ray(g, th, 0, 0)
+        for method in ("siddon", "brute"):
+            got = _entries_dict(*oracle.ray_entries(g, S, D, method), 1e-12)
+            assert got.keys() == want.keys(), (c, method, got)
+            for k in want:
+                assert abs(got[k] - want[k]) <= 1e-12, (c, method, k)
+
+
+def _box_chord(S, D, lo, hi):
+    """Length of the segment S->D inside the axis-aligned box [lo, hi] (numpy slab test)."""
+    d = D - S
+    a0, a1 = 0.0, 1.0
+    for a in range(3):
+        if d[a] == 0:
+            if not (lo[a] <= S[a] < hi[a]):
+                return 0.0
+            continue
+        t0, t1 = sorted(((lo[a] - S[a]) / d[a], (hi[a] - S[a]) / d[a]))
+        a0, a1 = max(a0, t0), min(a1, t1)
+    return max(a1 - a0, 0.0) * float(np.linalg.norm(d))
+
+
+def test_row_sums_equal_volume_chord():
+    """sum_j a_ij = length of ray i inside the whole volume box: no gaps, no double counts."""
+    cfg = synth.config("c1")
+    g = synth.make_geometry(cfg).subset([0])
+    M = oracle.FrameMatrix(g, 0)
+    rs = M.A(np.ones(g.n_vox))
+    half = np.array([g.nx, g.ny, g.nz]) / 2.0
+    rng = np.random.default_rng(1)
+    for r in rng.integers(0, M.nrows, size=300):
+        view, rem = divmod(int(r), g.nu * g.nv)
+        iv, iu = divmod(rem, g.nu)
+        S, D = oracle.ray(g, g.angles[view], iu, iv)
+        assert abs(rs[r] - _box_chord(S, D, -half, half)) <= 1e-11
+
+
+def test_box_phantom_exact():
+    """A voxel-aligned box of value mu projects to mu x chord through the box (exact)."""
+    cfg = synth.config("c1")
+    g = synth.make_geometry(cfg).subset([1])
+    x = np.zeros((g.nz, g.ny, g.nx))
+    lo_i, hi_i = (5, 9, 12), (20, 27, 22)     # i, j, k ranges [lo, hi)
+    x[lo_i[2]:hi_i[2], lo_i[1]:hi_i[1], lo_i[0]:hi_i[0]] = 0.037
+    y = oracle.FrameMatrix(g, 0).A(x)
+    lo = np.array([lo_i[a] - [g.nx, g.ny, g.nz][a] / 2.0 for a in range(3)])
+    hi = np.array([hi_i[a] - [g.nx, g.ny, g.nz][a] / 2.0 for a in range(3)])
+    rng = np.random.default_rng(2)
+    for r in rng.integers(0, len(y), size=400):
+        view, rem = divmod(int(r), g.nu * g.nv)
+        iv, iu = divmod(rem, g.nu)
+        S, D = oracle.ray(g, g.angles[view], iu, iv)
+        assert abs(y[r] - 0.037 * _box_chord(S, D, lo, hi)) <= 1e-12
+
+
+def _ellipsoid_integral(S, D, shape, centre):
+    """Analytic line integral of mu over an ellipsoid (quadratic in the unit-sphere frame)."""
+    Rt = shape.rot.T
+    s = (Rt @ (S - centre)) / shape.axes
+    d = (Rt @ (D - S)) / shape.axes
+    a, b, c = d @ d, s @ d, s @ s - 1.0
+    disc = b * b - a * c
+    if disc <= 0:
+        return 0.0
+    return shape.mu * 2.0 * math.sqrt(disc) / a * float(np.linalg.norm(D - S))
+
+
+def test_projector_converges_to_analytic_ellipsoids():
+    """A(voxelised ellipsoids) -> analytic line integrals, error shrinking with resolution."""
+    errs = []
+    for n in (16, 32, 64):
+        cfg = dataclasses.replace(synth.config("c1"), cid=77, n=(n, n, n), det=(int(1.5 * n), int(1.5 * n)),
+                                  src_iso=6.25 * n, src_det=12.5 * n, n_objects=3, n_frames=1, views=2)
+        g = synth.make_geometry(cfg)
+        shapes = synth.make_shapes(cfg)
+        x = synth.make_phantom(cfg, shapes=shapes)[0]
+        y = oracle.FrameMatrix(g, 0).A(x)
+        ref = np.zeros_like(y)
+        for r in range(len(y)):
+            view, rem = divmod(r, g.nu * g.nv)
+            iv, iu = divmod(rem, g.nu)
+            S, D = oracle.ray(g, g.angles[view], iu, iv)
+            ref[r] = sum(_ellipsoid_integral(S, D, s, synth.frame_centre(s, cfg, 0)) for s in shapes)
+        errs.append(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    # first-order convergence (objects are only 1-13 voxels across), frozen from the oracle:
+    # 0.174, 0.088, 0.046 at 16^3, 32^3, 64^3
+    assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1], errs
+    assert errs[2] < 0.06, errs
+
+
+def test_quarter_turn_symmetry():
+    """Rotating the volume by 90 degrees about z and the scanner by 90 degrees reproduces the sinogram."""
+    n = 12
+    g = _geom(n=(n, n, 7), det=(17, 9), rs=75.0, rsd=150.0, angles=(0.37, 2.1))
+    g90 = _geom(n=(n, n, 7), det=(17, 9), rs=75.0, rsd=150.0, angles=(0.37 + math.pi / 2, 2.1 + math.pi / 2))
+    rng = np.random.default_rng(3)
+    x = rng.uniform(size=(7, n, n))
+    # x'(R p) = x(p) with R the +90 degree turn: x'[k, a, b] = x[k, n-1-b, a]
+    xr = np.empty_like(x)
+    for a in range(n):
+        for b in range(n):
+            xr[:, a, b] = x[:, n - 1 - b, a]
+    y = oracle.FrameMatrix(g, 0).A(x)
+    y90 = oracle.FrameMatrix(g90, 0).A(xr)
+    assert np.abs(y - y90).max() <= 1e-10 * np.abs(y).max()
+
+
+def test_transpose_dot_product():
+    """<A x, y> = <x, A^T y> for the CSR transpose (FP64, 1e-13 rel)."""
+    cfg = synth.config("c1")
+    g = synth.make_geometry(cfg)
+    M = oracle.FrameMatrix(g, 2)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(M.ncols)
+    y = rng.standard_normal(M.nrows)
+    lhs, rhs = M.A(x) @ y, x @ M.AT(y)
+    assert abs(lhs - rhs) <= 1e-13 * max(abs(lhs), 1.0) * 10
+    # and the transpose equals the dense transpose on a tiny problem
+    gt = synth.make_geometry(synth.config("tiny8"))
+    Mt = oracle.FrameMatrix(gt, 1)
+    Ad = Mt.dense()
+    yy = rng.standard_normal(Mt.nrows)
+    assert np.allclose(Mt.AT(yy), Ad.T @ yy, rtol=0, atol=1e-12)
+
+
+def test_sampled_ray_and_voxel_routines_match_csr():
+    cfg = synth.config("c1")
+    g = synth.make_geometry(cfg)
+    f = 3
+    M = oracle.FrameMatrix(g, f)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(size=M.ncols)
+    y = rng.uniform(size=M.nrows)
+    rows = rng.integers(0, M.nrows, size=50)
+    vw, rem = np.divmod(rows, g.nu * g.nv)
+    iv, iu = np.divmod(rem, g.nu)
+    assert np.allclose(oracle.project_rays(g, f, vw, iv, iu, x), M.A(x)[rows], rtol=1e-13, atol=1e-13)
+    vox = rng.integers(0, M.ncols, size=20)
+    assert np.allclose(oracle.backproject_voxels(g, f, y, vox), M.AT(y)[vox], rtol=1e-12, atol=1e-12)
+
+
+def test_rays_missing_volume_are_zero_rows():
+    """A detector much wider than the volume: outer rays miss and their rows are empty."""
+    g = _geom(n=(6, 6, 6), det=(40, 3), rs=30.0, rsd=60.0, angles=(0.2,))
+    M = oracle.FrameMatrix(g, 0)
+    counts = np.diff(M.rowptr).reshape(g.nv, g.nu)
+    assert (counts[:, :5] == 0).all() and (counts[:, -5:] == 0).all()
+    assert (counts[:, 18:22] > 0).all()
