@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched forward-model proximal map on one MI355X.
+
+One step = one call of the whole hot path on one batch: the proximal map of
+the data term (paper eq. (mace_L)) for all 16 frames of the 128^3 x 16
+workload (192^2 detector, 16 interlaced views per frame over 360 degrees),
+solved by the HIP library's batched CG to the frozen stopping rule.  Inputs
+are resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  Metric: voxel.views per second of solved proximal maps
+(sum over frames of voxels x views, divided by the wall time of the solve).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "prox-map voxel·views/s at 1e-4 rel err: learned+batched vs plain CG; HBM GB/s"
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+
+# residual tolerance per workload, frozen from the parity test against the
+# FP64 oracle (relative error of x <= 1e-4 at this recursive residual)
+FROZEN_TOL = {"c2": 1e-6, "c1": 1e-8, "c2s": 1e-6, "c3s": 1e-7}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--max-iter", type=int, default=6000)
+    ap.add_argument("--check-every", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=40, help="FP64 CG iterations timed in the CPU sample")
+    ap.add_argument("--tiles", default="", help="rays_per_lane,waves_per_group,xcd_remap (default: plan default)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, geom, v_np, y_np, lam_np, gpu_iters, n_iter):
+    """The FP64 oracle on a bounded sample: frame 0 of the same workload, CSR
+    build + transpose + n_iter CG iterations, scaled to the iteration count the
+    GPU needed for that frame."""
+    import numpy as np
+    import oracle
+    g0 = geom.subset([0])
+    s0 = geom.sino_slice(0)
+    t0 = time.perf_counter()
+    M = oracle.FrameMatrix(g0, 0)
+    M._transpose()
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, st = M.prox_cg(v_np[0].astype(np.float64), y_np[s0].astype(np.float64), lam_np[s0].astype(np.float64),
+                      cfg.sigma, tol=0.0, max_iter=n_iter)
+    t_cg = time.perf_counter() - t0
+    per_iter = t_cg / max(n_iter, 1)
+    t_frame = t_build + per_iter * gpu_iters
+    vv = g0.n_vox * g0.views_of(0)
+    return {"value": vv / t_frame, "unit": "voxel·views/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "frame 0 of the same batch (%d^3 voxels x %d views, nnz %d): FP64 CSR build %.2fs + "
+                      "%d FP64 CG iterations timed (%.3fs/iter), scaled to the %d iterations the GPU took on "
+                      "that frame" % (geom.nx, g0.views_of(0), M.nnz, t_build, n_iter, per_iter, gpu_iters)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU; the proximal map shards by frame across GPUs "
+              "(design only), so --gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2008_01567_amd import msf, synth
+
+    dev = torch.device("cuda:0")
+    cfg = synth.config(args.config)
+    geom = synth.make_geometry(cfg)
+    tol = args.tol if args.tol is not None else FROZEN_TOL.get(args.config, cfg.tol)
+    t0 = time.perf_counter()
+    x0 = synth.make_phantom(cfg, dtype=np.float32)
+    v_np = synth.make_v(cfg, x0.astype(np.float64)).astype(np.float32)
+    plan = msf.Plan(geom)
+    if args.tiles:
+        r, w, xr = (int(t) for t in args.tiles.split(","))
+        plan.set_tiles(rays_per_lane=r, waves_per_group=w, back_mode=0, xcd_remap=xr)
+    y_clean = plan.project(torch.from_numpy(x0).to(dev)).cpu().numpy()
+    eps = synth.noise_eps(cfg, geom, dtype=np.float32)
+    y_np, lam_np = synth.finish_measurement(y_clean, eps, synth.frame_counts(geom), geom.n_rays_per_view,
+                                            dtype=np.float32)
+    v = torch.from_numpy(v_np).to(dev)
+    y = torch.from_numpy(y_np).to(dev)
+    lam = torch.from_numpy(lam_np).to(dev)
+    out = torch.empty_like(v)
+    nnz = plan.count_intersections()
+    log("setup %.1fs, nnz per frame %s" % (time.perf_counter() - t0, nnz[:4].tolist()))
+
+    def solve():
+        return plan.prox_solve(v, y, lam, cfg.sigma, tol=tol, max_iter=args.max_iter,
+                               check_every=args.check_every, use_graph=True, out=out)
+
+    for i in range(args.warmup):
+        _, st = solve()
+        log("warmup %d: iters %s steps %d %.3fs" % (i, st["iters"].tolist(), st["steps"], st["seconds"]))
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        _, st = solve()
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    st = stats[-1]
+    log("step: %.3fs, iters %s, status %d" % (dt, st["iters"].tolist(), st["status"]))
+    tm = plan.get_timing()
+    fwd_ms = tm["forward_ms"] / max(tm["forward_launches"], 1)
+    back_ms = tm["back_ms"] / max(tm["back_launches"], 1)
+    dominant, dom_ms = ("forward projector k_forward", fwd_ms) if fwd_ms >= back_ms else \
+        ("backprojector k_back_scatter", back_ms)
+    nnz_total = int(nnz.sum())
+    flops = 2.0 * nnz_total        # one FMA per ray-voxel intersection (SpMV convention)
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    voxel_views = geom.voxel_views()
+    value = voxel_views / dt
+    result = {
+        "metric": METRIC, "value": value, "unit": "voxel·views/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%s: prox map %dx%dx%d x %d frames, detector %dx%d, %d views/frame (%s), "
+                               "sigma %.2g, stop at rel. residual %.0e" %
+                               (args.config, geom.nx, geom.ny, geom.nz, geom.n_frames, geom.nu, geom.nv,
+                                geom.views_of(0), cfg.schedule, cfg.sigma, tol),
+                   "solver": "plain batched CG (FP32 vectors, FP64 scalars), hipGraph per %d steps" %
+                             args.check_every,
+                   "tiles": plan.get_tiles()},
+        "cg_iters": {"mean": float(np.mean(st["iters"])), "max": int(np.max(st["iters"]))},
+        "kernels_ms": {"forward": fwd_ms, "back": back_ms, "timed_launches": tm["forward_launches"]},
+        "nnz_A": nnz_total,
+        "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(cfg, geom, v_np, y_np, lam_np, int(st["iters"][0]), args.cpu_iters)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

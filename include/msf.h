@@ -1,0 +1,189 @@
+/*
+ * msf.h - C ABI of libmsf.so: the forward-model proximal map of multi-slice
+ * fusion for 4D cone-beam CT (Majee et al., "Multi-Slice Fusion for
+ * Sparse-View and Limited-Angle 4D CT Reconstruction"), built for MI355X
+ * (gfx950).
+ *
+ * The operation (paper Sec. II, eqs. (LL_time_expand) and Sec. III,
+ * eq. (mace_L)): for each time frame n,
+ *
+ *     x_n = argmin_z  1/2 || y_n - A_n z ||^2_{Lambda_n} + || v_n - z ||^2 / (2 sigma^2)
+ *
+ * which is the solution of (A_n^T Lambda_n A_n + sigma^-2 I) z = A_n^T Lambda_n y_n + sigma^-2 v_n.
+ * The data term is separable over time frames (eq. (LL_time_expand)), so every
+ * frame is an independent problem; the library solves all of them in one
+ * batch.  A_n is the cone-beam system matrix: A_n[i][j] is the length of the
+ * segment from the point source to the centre of detector pixel i inside
+ * voxel j (exact ray-voxel intersection lengths, computed on the fly).
+ *
+ * Geometry (all lengths in voxel units, voxel side 1, origin at the volume
+ * centre; the object-rotation of the paper's Sec. II is modelled as a
+ * rotating source/detector pair):
+ *   voxel (i,j,k) spans [i - nx/2, i + 1 - nx/2) x [j - ny/2, ...) x [k - nz/2, ...)
+ *     (half-open on every axis);
+ *   view angle t: source S = (src_iso cos t, src_iso sin t, 0), detector
+ *     centre D0 = S + src_det (-cos t, -sin t, 0), detector axes
+ *     e_u = (-sin t, cos t, 0), e_v = (0, 0, 1);
+ *   pixel (iu, iv) centre = D0 + u e_u + v e_v with
+ *     u = (iu - (nu-1)/2) du + det_off_u,  v = (iv - (nv-1)/2) dv + det_off_v.
+ *
+ * Layouts of caller arrays (FP32, contiguous, C order):
+ *   volumes   [n_frames][nz][ny][nx]      (x fastest)
+ *   sinograms the frames' views concatenated; frame n owns views
+ *             view_offset[n] .. view_offset[n+1]-1; each view is [nv][nu]
+ *             (u fastest).  Lambda (the diagonal weights) has the same layout.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller unless
+ * marked "host".  The library never frees or retains caller memory after a
+ * call returns.  A plan owns all device workspace (sized at creation) and is
+ * not thread-safe: calls on one plan must not overlap.  Work is enqueued on the
+ * caller's HIP stream (`stream` is a hipStream_t; NULL = the default stream);
+ * calls that return statistics synchronise that stream before returning.
+ *
+ * Errors: functions return msf_status.  On MSF_EINVAL nothing is written to
+ * the outputs.  HIP runtime failures return MSF_EHIP.  msf_last_error() gives
+ * a message for the last failing call on the calling thread.  No C++
+ * exception crosses this interface.
+ */
+#ifndef MSF_H
+#define MSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum msf_status {
+    MSF_OK = 0,
+    MSF_NOT_CONVERGED = 1,   /* warning: some frame hit max_iter; outputs and stats are valid */
+    MSF_CNN_FALLBACK = 2,    /* warning: the learned start was rejected on some frame (v used) */
+    MSF_EINVAL = -1,         /* invalid argument; outputs untouched */
+    MSF_ENOMEM = -2,         /* device allocation failed */
+    MSF_EHIP = -3,           /* HIP runtime error */
+    MSF_EBREAKDOWN = -4      /* CG breakdown (<p, H p> <= 0 or non-finite) on some frame */
+} msf_status;
+
+/* Scan description.  view_offset and angles are HOST arrays, copied at plan
+ * creation. */
+typedef struct msf_geometry {
+    int32_t nx, ny, nz;          /* voxels per frame (x fastest) */
+    int32_t n_frames;            /* time frames (>= 1) */
+    int32_t nu, nv;              /* detector columns (fast axis) and rows */
+    double du, dv;               /* pixel pitch on the detector plane (> 0) */
+    double src_iso;              /* source to rotation axis distance (> half volume diagonal) */
+    double src_det;              /* source to detector distance (> src_iso) */
+    double det_off_u, det_off_v; /* detector centre offset along e_u, e_v */
+    const int64_t *view_offset;  /* host [n_frames + 1], non-decreasing, view_offset[0] = 0 */
+    const double *angles;        /* host [view_offset[n_frames]], radians */
+} msf_geometry;
+
+typedef struct msf_plan msf_plan;
+typedef struct msf_cnn msf_cnn;
+
+/* Kernel launch shapes (chosen by the autotuner, or defaults). */
+typedef struct msf_tiles {
+    int32_t rays_per_lane;       /* forward/back projector: rays of one detector column per lane: 1, 2 or 4 */
+    int32_t waves_per_group;     /* projector workgroup size in 64-lane waves: 1, 2 or 4 */
+    int32_t back_mode;           /* 0 = ray-driven scatter (atomic adds), 1 = voxel-driven gather */
+    int32_t xcd_remap;           /* 1 = keep a frame's tiles on one XCD (L2 locality) */
+} msf_tiles;
+
+enum { MSF_X0_V = 0, MSF_X0_USER = 1, MSF_X0_CNN = 2 };
+
+typedef struct msf_solve_opts {
+    double tol;                  /* stop frame n once ||b_n - H_n x_n|| <= tol ||b_n|| (recursive residual) */
+    int32_t max_iter;            /* CG steps per frame (>= 0) */
+    int32_t check_every;         /* host checks for all-frames-converged every this many steps (>= 1) */
+    int32_t x0_mode;             /* MSF_X0_V: start from v; MSF_X0_USER: from x0; MSF_X0_CNN: from cnn */
+    int32_t use_graph;           /* 1: replay each CG step as one captured hipGraph */
+    int32_t true_residual;       /* 1: recompute ||b - H x|| / ||b|| at the end (one more A, A^T) */
+    int32_t reserved;
+    const float *x0;             /* device [n_frames][nz][ny][nx], MSF_X0_USER only */
+    const msf_cnn *cnn;          /* MSF_X0_CNN only */
+} msf_solve_opts;
+
+typedef struct msf_solve_stats {
+    int32_t *iters;              /* host [n_frames] or NULL: CG steps taken per frame */
+    double *rel_residual;        /* host [n_frames] or NULL: recursive ||r|| / ||b|| at exit */
+    double *true_rel_residual;   /* host [n_frames] or NULL: recomputed (true_residual = 1), else -1 */
+    uint8_t *converged;          /* host [n_frames] or NULL */
+    uint8_t *cnn_used;           /* host [n_frames] or NULL: 1 if the learned start was kept */
+    int32_t steps;               /* out: CG steps launched for the batch */
+    int32_t reserved;
+    double seconds;              /* out: wall time of the call (host clock) */
+} msf_solve_stats;
+
+/* Fill *opts with defaults: tol 1e-6, max_iter 1000, check_every 8, start from v,
+ * graphs on, no true residual. */
+void msf_solve_opts_default(msf_solve_opts *opts);
+
+/* Create a plan for one geometry: validates it (EINVAL on non-positive sizes
+ * or pitches, src_det <= src_iso, a source inside the volume's bounding
+ * cylinder, bad view_offset), copies the view tables to the device and
+ * allocates the solver workspace (5 volumes + 3 sinograms FP32).  *out is set
+ * only on success. */
+msf_status msf_plan_create(const msf_geometry *geom, msf_plan **out);
+
+/* Release a plan and its workspace (NULL is a no-op).  Synchronises the device. */
+void msf_plan_destroy(msf_plan *plan);
+
+/* Replace / read the plan's launch shapes.  EINVAL on an unsupported shape. */
+msf_status msf_plan_set_tiles(msf_plan *plan, const msf_tiles *tiles);
+msf_status msf_plan_get_tiles(const msf_plan *plan, msf_tiles *tiles);
+
+/* Number of nonzeros of A (ray-voxel intersections) is not stored; the
+ * per-plan sizes are reported here (host outputs, any may be NULL). */
+msf_status msf_plan_sizes(const msf_plan *plan, int64_t *n_vox_total, int64_t *n_meas_total,
+                          int64_t *workspace_bytes);
+
+/* y = A x for every frame (paper eq. (LL_time_expand)).  x: device volume
+ * [n_frames][nz][ny][nx]; y: device sinogram (all views), overwritten. */
+msf_status msf_project(msf_plan *plan, const float *x, float *y, void *stream);
+
+/* x = A^T y for every frame, the exact adjoint of msf_project (same lengths).
+ * y: device sinogram; x: device volume, overwritten. */
+msf_status msf_backproject(msf_plan *plan, const float *y, float *x, void *stream);
+
+/* The proximal map of the data term (paper eq. (mace_L)) for every frame, by
+ * conjugate gradients batched over frames: FP32 vectors, FP64 step sizes,
+ * inner products and residual norms.  v: device volume; y, lambda: device
+ * sinograms (lambda >= 0 and finite, else EINVAL); sigma > 0; x_out: device
+ * volume (may alias v).  opts NULL = defaults.  stats: host, may be NULL.
+ * Returns MSF_OK, MSF_NOT_CONVERGED (warning), MSF_CNN_FALLBACK (warning),
+ * MSF_EBREAKDOWN (x_out holds the last iterate) or an error. */
+msf_status msf_prox_solve(msf_plan *plan, const float *v, const float *y, const float *lambda, double sigma,
+                          const msf_solve_opts *opts, float *x_out, msf_solve_stats *stats, void *stream);
+
+/* Live kernel timing.  While enabled, msf_prox_solve records HIP events on
+ * the caller's stream around every forward-projector and backprojector launch
+ * of its CG steps (also inside captured graphs) and accumulates the elapsed
+ * times of the steps in which every frame was still iterating (launches that
+ * processed the whole batch).  Enabling resets the accumulators. */
+typedef struct msf_timing {
+    double forward_ms;           /* summed duration of the timed forward-projector launches */
+    int64_t forward_launches;
+    double back_ms;              /* summed duration of the timed backprojector launches */
+    int64_t back_launches;
+} msf_timing;
+msf_status msf_plan_set_timing(msf_plan *plan, int32_t enable);
+msf_status msf_plan_get_timing(const msf_plan *plan, msf_timing *out);
+
+/* Number of ray-voxel pieces of positive length (the nonzeros of A_n) per
+ * frame, counted by the forward projector's own traversal.  per_frame: host
+ * [n_frames].  Synchronises the stream. */
+msf_status msf_count_intersections(msf_plan *plan, int64_t *per_frame, void *stream);
+
+/* Message describing the last error on this thread ("" if none).  Valid until
+ * the next call on the same thread. */
+const char *msf_last_error(void);
+
+/* Library version string (static storage). */
+const char *msf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSF_H */

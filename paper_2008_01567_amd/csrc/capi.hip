@@ -1,0 +1,511 @@
+// Host side of the C ABI declared in include/msf.h: argument validation,
+// plan/workspace management, layout conversion at the boundary, and the
+// batched CG driver of the proximal map (paper Sec. III, eq. (mace_L)).
+#include "msf_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+int64_t vol_chunk();
+
+namespace {
+thread_local std::string g_err;
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+template <class T>
+hipError_t dalloc(T **p, size_t count, int64_t &total)
+{
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    total += (int64_t)bytes;
+    return hipMalloc((void **)p, bytes);
+}
+
+void free_plan_memory(msf_plan *P)
+{
+    if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    P->graph = nullptr;
+    P->graph_valid = false;
+    void *ptrs[] = {P->d_cs, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
+                    P->sy, P->slam, P->sz, P->part_proj, P->part_vol, P->scal, P->iscal, P->consts,
+                    P->flags};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (P->host_stage) (void)hipHostFree(P->host_stage);
+    P->host_stage = nullptr;
+    for (hipEvent_t e : P->ev)
+        if (e) (void)hipEventDestroy(e);
+    P->ev.clear();
+}
+
+// Detector rows that can meet the volume: a ray of row v has height
+// z = v_pos * t / L_xy at xy distance t from the source; inside the volume's
+// bounding cylinder t >= src_iso - r_max, so rows beyond the bound below stay
+// outside the z slab along their whole length (their matrix rows are empty).
+void row_range(msf_plan &P)
+{
+    const double rmax = std::sqrt(0.25 * P.nx * P.nx + 0.25 * P.ny * P.ny);
+    const double umax = 0.5 * (P.nu - 1) * P.du + std::fabs(P.offu);
+    const double lmax = std::sqrt(P.rsd * P.rsd + umax * umax);
+    const double bound = 0.5 * P.nz * lmax / (P.rs - rmax) + 1e-6 * P.nz + P.dv;
+    P.iv_lo = 0;
+    P.iv_hi = -1;
+    int lo = -1, hi = -1;
+    for (int iv = 0; iv < P.nv; ++iv) {
+        const double zp = (iv - 0.5 * (P.nv - 1)) * P.dv + P.offv;
+        if (std::fabs(zp) <= bound) {
+            if (lo < 0) lo = iv;
+            hi = iv;
+        }
+    }
+    if (lo >= 0) {
+        P.iv_lo = lo;
+        P.iv_hi = hi;
+    }
+}
+
+msf_status setup_tiles(msf_plan &P)
+{
+    const int rpc = 64 * P.tiles.rays_per_lane;
+    const int64_t n_ug = (P.nu + P.tiles.waves_per_group - 1) / P.tiles.waves_per_group;
+    const int64_t n_vc = P.iv_hi >= P.iv_lo ? (P.iv_hi - P.iv_lo + rpc) / rpc : 0;
+    P.tile_offset.assign(P.nf + 1, 0);
+    for (int f = 0; f <= P.nf; ++f) P.tile_offset[f] = P.view_offset[f] * n_ug * n_vc;
+    const int64_t total = P.tile_offset.back();
+    if (total > 0x7fffffffLL) {
+        set_error("projector tile count exceeds the grid limit");
+        return MSF_EINVAL;
+    }
+    hipError_t e;
+    if (P.d_tile_offset) (void)hipFree(P.d_tile_offset);
+    if (P.part_proj) (void)hipFree(P.part_proj);
+    P.d_tile_offset = nullptr;
+    P.part_proj = nullptr;
+    int64_t dummy = 0;
+    if ((e = dalloc(&P.d_tile_offset, P.nf + 1, dummy)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = dalloc(&P.part_proj, (size_t)total, dummy)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMemcpy(P.d_tile_offset, P.tile_offset.data(), sizeof(int64_t) * (P.nf + 1),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy");
+    if (P.graph) (void)hipGraphExecDestroy(P.graph);
+    P.graph = nullptr;
+    P.graph_valid = false;
+    return MSF_OK;
+}
+
+bool tiles_ok(const msf_tiles &t)
+{
+    return (t.rays_per_lane == 1 || t.rays_per_lane == 2 || t.rays_per_lane == 4) &&
+           (t.waves_per_group == 1 || t.waves_per_group == 2 || t.waves_per_group == 4) &&
+           (t.back_mode == 0) && (t.xcd_remap == 0 || t.xcd_remap == 1);
+}
+
+#define HIPCHK(expr)                                         \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+    } while (0)
+
+// internal volume [f][ny][nx][nz] <-> public [f][nz][ny][nx]
+hipError_t vol_to_internal(const msf_plan &P, const float *in, float *out, int check, int32_t *flag, hipStream_t s)
+{
+    return launch_transpose(in, out, P.nf, P.nz, P.ny * P.nx, check, flag, s);
+}
+hipError_t vol_to_public(const msf_plan &P, const float *in, float *out, hipStream_t s)
+{
+    return launch_transpose(in, out, P.nf, P.ny * P.nx, P.nz, 0, nullptr, s);
+}
+// internal sinogram [view][nu][nv] <-> public [view][nv][nu]
+hipError_t sino_to_internal(const msf_plan &P, const float *in, float *out, int check, int32_t *flag, hipStream_t s)
+{
+    return launch_transpose(in, out, P.n_views, P.nv, P.nu, check, flag, s);
+}
+hipError_t sino_to_public(const msf_plan &P, const float *in, float *out, hipStream_t s)
+{
+    return launch_transpose(in, out, P.n_views, P.nu, P.nv, 0, nullptr, s);
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+msf_status hip_fail(hipError_t e, const char *where)
+{
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? MSF_ENOMEM : MSF_EHIP;
+}
+
+extern "C" {
+
+const char *msf_last_error(void) { return g_err.c_str(); }
+
+const char *msf_version(void) { return "msf 0.1 (gfx950)"; }
+
+void msf_solve_opts_default(msf_solve_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-6;
+    o->max_iter = 1000;
+    o->check_every = 8;
+    o->x0_mode = MSF_X0_V;
+    o->use_graph = 1;
+    o->true_residual = 0;
+}
+
+msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
+{
+    g_err.clear();
+    if (!g || !out) { set_error("null geometry or output pointer"); return MSF_EINVAL; }
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || g->n_frames <= 0 || g->nu <= 0 || g->nv <= 0) {
+        set_error("sizes must be positive"); return MSF_EINVAL;
+    }
+    if ((int64_t)g->nx * g->ny * g->nz > 0x7fffffffLL || (int64_t)g->nu * g->nv > 0x7fffffffLL) {
+        set_error("per-frame volume or per-view detector exceeds 2^31 elements"); return MSF_EINVAL;
+    }
+    if (!finite_pos(g->du) || !finite_pos(g->dv) || !finite_pos(g->src_iso) || !finite_pos(g->src_det) ||
+        !std::isfinite(g->det_off_u) || !std::isfinite(g->det_off_v)) {
+        set_error("pitches and distances must be positive and finite"); return MSF_EINVAL;
+    }
+    const double rmax = std::sqrt(0.25 * g->nx * g->nx + 0.25 * g->ny * g->ny);
+    if (!(g->src_iso > rmax) || !(g->src_det > g->src_iso + rmax)) {
+        set_error("source and detector must lie outside the volume's bounding cylinder"); return MSF_EINVAL;
+    }
+    if (!g->view_offset || g->view_offset[0] != 0) { set_error("view_offset must start at 0"); return MSF_EINVAL; }
+    for (int f = 0; f < g->n_frames; ++f)
+        if (g->view_offset[f + 1] < g->view_offset[f]) { set_error("view_offset must be non-decreasing"); return MSF_EINVAL; }
+    const int64_t nviews = g->view_offset[g->n_frames];
+    if (nviews > 0 && !g->angles) { set_error("null angles"); return MSF_EINVAL; }
+    for (int64_t i = 0; i < nviews; ++i)
+        if (!std::isfinite(g->angles[i])) { set_error("non-finite angle"); return MSF_EINVAL; }
+
+    msf_plan *P = new (std::nothrow) msf_plan();
+    if (!P) { set_error("host allocation failed"); return MSF_ENOMEM; }
+    P->nx = g->nx; P->ny = g->ny; P->nz = g->nz; P->nf = g->n_frames; P->nu = g->nu; P->nv = g->nv;
+    P->du = g->du; P->dv = g->dv; P->rs = g->src_iso; P->rsd = g->src_det;
+    P->offu = g->det_off_u; P->offv = g->det_off_v;
+    P->view_offset.assign(g->view_offset, g->view_offset + g->n_frames + 1);
+    P->angles.assign(g->angles, g->angles + nviews);
+    P->n_views = nviews;
+    P->nvox = (int64_t)g->nx * g->ny * g->nz;
+    P->nvox_total = P->nvox * g->n_frames;
+    P->nmeas_total = nviews * (int64_t)g->nu * g->nv;
+    P->vol_blocks_per_frame = (P->nvox + vol_chunk() - 1) / vol_chunk();
+    P->tiles.rays_per_lane = 2;
+    P->tiles.waves_per_group = 4;
+    P->tiles.back_mode = 0;
+    P->tiles.xcd_remap = 1;
+    row_range(*P);
+
+    auto fail = [&](msf_status st) { free_plan_memory(P); delete P; return st; };
+    hipError_t e;
+    int64_t &tot = P->workspace_bytes;
+    std::vector<double2> cs(std::max<int64_t>(nviews, 1));
+    for (int64_t i = 0; i < nviews; ++i) cs[i] = make_double2(std::cos(P->angles[i]), std::sin(P->angles[i]));
+    if ((e = dalloc(&P->d_cs, (size_t)std::max<int64_t>(nviews, 1), tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->d_view_offset, P->nf + 1, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    float **vols[] = {&P->x, &P->r, &P->p, &P->vin};
+    for (float **v : vols)
+        if ((e = dalloc(v, (size_t)P->nvox_total, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc volume"));
+    if ((e = dalloc(&P->bp, (size_t)P->nvox_total, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc volume"));
+    float **sinos[] = {&P->sy, &P->slam, &P->sz};
+    for (float **v : sinos)
+        if ((e = dalloc(v, (size_t)P->nmeas_total, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc sinogram"));
+    if ((e = dalloc(&P->part_vol, (size_t)(P->nf * P->vol_blocks_per_frame), tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->scal, (size_t)SC_COUNT * P->nf, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->iscal, (size_t)IS_COUNT * P->nf, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->consts, 4, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->flags, 4, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    P->host_stage_bytes = sizeof(double) * (SC_COUNT * P->nf + 8) + sizeof(int32_t) * (IS_COUNT * P->nf + 8);
+    if ((e = hipHostMalloc(&P->host_stage, P->host_stage_bytes, hipHostMallocDefault)) != hipSuccess)
+        return fail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipMemcpy(P->d_cs, cs.data(), sizeof(double2) * cs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
+    if ((e = hipMemcpy(P->d_view_offset, P->view_offset.data(), sizeof(int64_t) * (P->nf + 1), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
+    // sinogram rows outside [iv_lo, iv_hi] are never written by the kernels: keep them zero
+    for (float **v : sinos)
+        if ((e = hipMemset(*v, 0, sizeof(float) * std::max<int64_t>(P->nmeas_total, 1))) != hipSuccess)
+            return fail(hip_fail(e, "hipMemset"));
+    if ((e = hipMemset(P->bp, 0, sizeof(double) * std::max<int64_t>(P->nvox_total, 1))) != hipSuccess)
+        return fail(hip_fail(e, "hipMemset"));
+    msf_status st = setup_tiles(*P);
+    if (st != MSF_OK) return fail(st);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(hip_fail(e, "hipDeviceSynchronize"));
+    *out = P;
+    return MSF_OK;
+}
+
+void msf_plan_destroy(msf_plan *P)
+{
+    if (!P) return;
+    (void)hipDeviceSynchronize();
+    free_plan_memory(P);
+    delete P;
+}
+
+msf_status msf_plan_set_tiles(msf_plan *P, const msf_tiles *t)
+{
+    g_err.clear();
+    if (!P || !t) { set_error("null argument"); return MSF_EINVAL; }
+    if (!tiles_ok(*t)) { set_error("unsupported tile shape"); return MSF_EINVAL; }
+    const msf_tiles old = P->tiles;
+    P->tiles = *t;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    msf_status st = setup_tiles(*P);
+    if (st != MSF_OK) {
+        P->tiles = old;
+        setup_tiles(*P);
+    }
+    return st;
+}
+
+msf_status msf_plan_get_tiles(const msf_plan *P, msf_tiles *t)
+{
+    if (!P || !t) { set_error("null argument"); return MSF_EINVAL; }
+    *t = P->tiles;
+    return MSF_OK;
+}
+
+msf_status msf_plan_sizes(const msf_plan *P, int64_t *nv, int64_t *nm, int64_t *wb)
+{
+    if (!P) { set_error("null plan"); return MSF_EINVAL; }
+    if (nv) *nv = P->nvox_total;
+    if (nm) *nm = P->nmeas_total;
+    if (wb) *wb = P->workspace_bytes;
+    return MSF_OK;
+}
+
+msf_status msf_project(msf_plan *P, const float *x, float *y, void *stream)
+{
+    g_err.clear();
+    if (!P || !x || !y) { set_error("null argument"); return MSF_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(vol_to_internal(*P, x, P->p, 0, nullptr, s));
+    HIPCHK(launch_forward(*P, PM_PLAIN, P->p, nullptr, P->sz, false, s));
+    HIPCHK(sino_to_public(*P, P->sz, y, s));
+    return MSF_OK;
+}
+
+msf_status msf_backproject(msf_plan *P, const float *y, float *x, void *stream)
+{
+    g_err.clear();
+    if (!P || !x || !y) { set_error("null argument"); return MSF_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(sino_to_internal(*P, y, P->sz, 0, nullptr, s));
+    HIPCHK(launch_fill_d(P->bp, P->nvox_total, s));
+    HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_d2f(P->bp, P->p, P->nvox_total, s));
+    HIPCHK(vol_to_public(*P, P->p, x, s));
+    HIPCHK(launch_fill_d(P->bp, P->nvox_total, s));
+    return MSF_OK;
+}
+
+msf_status msf_plan_set_timing(msf_plan *P, int32_t enable)
+{
+    g_err.clear();
+    if (!P) { set_error("null plan"); return MSF_EINVAL; }
+    HIPCHK(hipDeviceSynchronize());
+    P->timing = enable != 0;
+    P->t_fwd_ms = P->t_back_ms = 0.0;
+    P->n_fwd = P->n_back = 0;
+    return MSF_OK;
+}
+
+msf_status msf_plan_get_timing(const msf_plan *P, msf_timing *t)
+{
+    if (!P || !t) { set_error("null argument"); return MSF_EINVAL; }
+    t->forward_ms = P->t_fwd_ms;
+    t->forward_launches = P->n_fwd;
+    t->back_ms = P->t_back_ms;
+    t->back_launches = P->n_back;
+    return MSF_OK;
+}
+
+msf_status msf_count_intersections(msf_plan *P, int64_t *per_frame, void *stream)
+{
+    g_err.clear();
+    if (!P || !per_frame) { set_error("null argument"); return MSF_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_forward(*P, PM_COUNT, P->p, nullptr, P->sz, false, s));
+    std::vector<float> h((size_t)std::max<int64_t>(P->nmeas_total, 1));
+    HIPCHK(hipMemcpyAsync(h.data(), P->sz, sizeof(float) * P->nmeas_total, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t per_view = (int64_t)P->nu * P->nv;
+    for (int f = 0; f < P->nf; ++f) {
+        int64_t c = 0;
+        for (int64_t i = P->view_offset[f] * per_view; i < P->view_offset[f + 1] * per_view; ++i) c += (int64_t)h[i];
+        per_frame[f] = c;
+    }
+    return MSF_OK;
+}
+
+msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const float *lam, double sigma,
+                          const msf_solve_opts *opts_in, float *x_out, msf_solve_stats *stats, void *stream)
+{
+    g_err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!P || !v || !y || !lam || !x_out) { set_error("null argument"); return MSF_EINVAL; }
+    if (!finite_pos(sigma)) { set_error("sigma must be positive and finite"); return MSF_EINVAL; }
+    msf_solve_opts o;
+    if (opts_in) o = *opts_in;
+    else msf_solve_opts_default(&o);
+    if (!(std::isfinite(o.tol) && o.tol >= 0.0) || o.max_iter < 0 || o.check_every < 1) {
+        set_error("invalid solver options (tol >= 0, max_iter >= 0, check_every >= 1)"); return MSF_EINVAL;
+    }
+    if (o.x0_mode == MSF_X0_USER && !o.x0) { set_error("x0_mode USER needs x0"); return MSF_EINVAL; }
+    if (o.x0_mode == MSF_X0_CNN) { set_error("x0_mode CNN needs msf_prox_solve_learned"); return MSF_EINVAL; }
+    if (o.x0_mode != MSF_X0_V && o.x0_mode != MSF_X0_USER) { set_error("unknown x0_mode"); return MSF_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    const int nf = P->nf;
+
+    // constants and input checks (validated before any output is written)
+    double *hc = (double *)P->host_stage;
+    int32_t *hflags = (int32_t *)(hc + 4);
+    hc[0] = 1.0 / (sigma * sigma);
+    hc[1] = o.tol;
+    hc[2] = (double)o.max_iter;
+    hc[3] = 0.0;
+    HIPCHK(hipMemcpyAsync(P->consts, hc, 4 * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(P->flags, 0, 4 * sizeof(int32_t), s));
+    HIPCHK(vol_to_internal(*P, v, P->vin, 1, P->flags + 2, s));
+    HIPCHK(sino_to_internal(*P, y, P->sy, 1, P->flags + 1, s));
+    HIPCHK(sino_to_internal(*P, lam, P->slam, 2, P->flags + 0, s));
+    if (o.x0_mode == MSF_X0_USER) HIPCHK(vol_to_internal(*P, o.x0, P->x, 1, P->flags + 3, s));
+    else HIPCHK(launch_copy(P->x, P->vin, P->nvox_total, s));
+    HIPCHK(hipMemcpyAsync(hflags, P->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hflags[0] || hflags[1] || hflags[2] || hflags[3]) {
+        set_error("invalid input: " + std::to_string(hflags[0]) + " negative/non-finite lambda, " +
+                  std::to_string(hflags[1]) + " non-finite y, " + std::to_string(hflags[2]) + " non-finite v, " +
+                  std::to_string(hflags[3]) + " non-finite x0");
+        return MSF_EINVAL;
+    }
+
+    // ||b|| with b = A^T Lambda y + v / sigma^2
+    HIPCHK(launch_sino_mul(P->slam, P->sy, P->sz, P->nmeas_total, s));
+    HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_vol_bnorm(*P, s));
+    HIPCHK(launch_scalar_reduce(*P, RW_BNORM, s));
+    // r = b - H x0, p = r
+    HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
+    HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_vol_init_residual(*P, s));
+    HIPCHK(launch_scalar_reduce(*P, RW_INIT, s));
+
+    // CG steps: one captured graph holds a whole check period (check_every
+    // steps of six launches each); a shorter last period runs eagerly.
+    const int period = o.check_every;
+    if (P->timing && (int)P->ev.size() < 4 * period) {
+        const size_t have = P->ev.size();
+        P->ev.resize(4 * period, nullptr);
+        for (size_t k = have; k < P->ev.size(); ++k) HIPCHK(hipEventCreate(&P->ev[k]));
+    }
+    bool use_graph = o.use_graph != 0;
+    if (use_graph && (!P->graph_valid || P->graph_steps != period || P->graph_timing != P->timing)) {
+        if (P->graph) (void)hipGraphExecDestroy(P->graph);
+        P->graph = nullptr;
+        P->graph_valid = false;
+        hipStream_t cs;
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = hipSuccess;
+            for (int k = 0; k < period && e2 == hipSuccess; ++k)
+                e2 = launch_cg_step(*P, cs, P->timing ? &P->ev[4 * k] : nullptr);
+            e = hipStreamEndCapture(cs, &graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&P->graph, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            if (!P->timing) return hip_fail(e, "CG step graph capture");
+            (void)hipGetLastError();   // timed steps fall back to eager launches
+            use_graph = false;
+        } else {
+            P->graph_valid = true;
+            P->graph_steps = period;
+            P->graph_timing = P->timing;
+        }
+    }
+    int32_t *hact = hflags;
+    int steps = 0;
+    std::vector<float> step_fwd_ms, step_back_ms;
+    HIPCHK(hipMemcpyAsync(hact, P->iscal + IS_ACTIVE * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool any = std::any_of(hact, hact + nf, [](int32_t a) { return a != 0; });
+    while (any && steps < o.max_iter) {
+        const int n = std::min(period, o.max_iter - steps);
+        if (use_graph && n == period) {
+            HIPCHK(hipGraphLaunch(P->graph, s));
+        } else {
+            for (int k = 0; k < n; ++k) HIPCHK(launch_cg_step(*P, s, P->timing ? &P->ev[4 * k] : nullptr));
+        }
+        steps += n;
+        HIPCHK(hipMemcpyAsync(hact, P->iscal + IS_ACTIVE * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (P->timing) {
+            for (int k = 0; k < n; ++k) {
+                float a = 0.0f, b = 0.0f;
+                HIPCHK(hipEventElapsedTime(&a, P->ev[4 * k], P->ev[4 * k + 1]));
+                HIPCHK(hipEventElapsedTime(&b, P->ev[4 * k + 2], P->ev[4 * k + 3]));
+                step_fwd_ms.push_back(a);
+                step_back_ms.push_back(b);
+            }
+        }
+        any = std::any_of(hact, hact + nf, [](int32_t a) { return a != 0; });
+    }
+
+    HIPCHK(vol_to_public(*P, P->x, x_out, s));
+    if (o.true_residual) {
+        HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
+        HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+        HIPCHK(launch_vol_true_residual(*P, s));
+        HIPCHK(launch_scalar_reduce(*P, RW_TRUE, s));
+    }
+    double *hs = (double *)P->host_stage;
+    int32_t *hi = (int32_t *)(hs + SC_COUNT * nf);
+    HIPCHK(hipMemcpyAsync(hs, P->scal, sizeof(double) * SC_COUNT * nf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hi, P->iscal, sizeof(int32_t) * IS_COUNT * nf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+
+    msf_status st = MSF_OK;
+    for (int f = 0; f < nf; ++f) {
+        const double rel = hs[SC_REL * nf + f];
+        const bool conv = hs[SC_BNORM * nf + f] > 0.0 ? rel <= o.tol : hs[SC_GAMMA * nf + f] == 0.0;
+        if (hi[IS_STATUS * nf + f] == MSF_EBREAKDOWN) st = MSF_EBREAKDOWN;
+        else if (!conv && st == MSF_OK) st = MSF_NOT_CONVERGED;
+        if (stats) {
+            if (stats->iters) stats->iters[f] = hi[IS_ITERS * nf + f];
+            if (stats->rel_residual) stats->rel_residual[f] = rel;
+            if (stats->true_rel_residual) stats->true_rel_residual[f] = o.true_residual ? hs[SC_TRUE * nf + f] : -1.0;
+            if (stats->converged) stats->converged[f] = conv ? 1 : 0;
+            if (stats->cnn_used) stats->cnn_used[f] = 0;
+        }
+    }
+    if (P->timing && !step_fwd_ms.empty()) {
+        // only steps in which every frame was still iterating: each such launch did the full batch
+        int full = o.max_iter;
+        for (int f = 0; f < nf; ++f) full = std::min(full, (int)hi[IS_ITERS * nf + f]);
+        for (int k = 0; k < full && k < (int)step_fwd_ms.size(); ++k) {
+            P->t_fwd_ms += step_fwd_ms[k];
+            P->t_back_ms += step_back_ms[k];
+            P->n_fwd++;
+            P->n_back++;
+        }
+    }
+    if (st == MSF_EBREAKDOWN) set_error("CG breakdown: <p, H p> <= 0 or non-finite on some frame");
+    if (stats) {
+        stats->steps = steps;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations of libmsf (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/msf.h"
+
+// ---------------------------------------------------------------------------
+// Internal layouts (chosen for the circular orbit about the z axis):
+//   volume   [frame][ny][nx][nz]   z fastest: all rays of one detector column
+//            (fixed u, varying v) share one xy path, and a 64-lane wave of
+//            consecutive detector rows reads consecutive z of one voxel column.
+//   sinogram [view][nu][nv]        v fastest: a wave's rows are contiguous.
+// The public layouts ([frame][nz][ny][nx], [view][nv][nu]) are converted at
+// the API boundary by a tiled transpose.
+// ---------------------------------------------------------------------------
+
+enum ProjMode : int {
+    PM_PLAIN = 0,     // out = A p
+    PM_WEIGHTED = 1,  // out = Lambda (A p), partial += <A p, Lambda A p>
+    PM_RESID = 2,     // out = Lambda (y - A p)
+    PM_COUNT = 3,     // out = number of ray-voxel pieces of each ray (nnz of its row of A)
+};
+
+// Everything a projector launch needs (passed by value as a kernel argument).
+struct ProjParams {
+    int nx, ny, nz, nu, nv, nf;
+    double du, dv, rs, rsd, offu, offv;
+    const double2 *cs;           // [n_views] (cos t, sin t)
+    const int64_t *view_offset;  // [nf + 1]
+    const int64_t *tile_offset;  // [nf + 1] projector tiles per frame (prefix)
+    const int32_t *active;       // [nf] or nullptr (all active)
+    int n_ug;                    // u-groups per view (columns / waves_per_group)
+    int n_vc;                    // row chunks per column
+    int rows_per_chunk;          // 64 * rays_per_lane
+    int iv_lo, iv_hi;            // detector rows that can meet the volume
+    int xcd_remap;
+    int64_t nvox;                // voxels per frame
+    int64_t total_tiles;
+};
+
+// Per-frame scalars of the batched CG (device, FP64).
+enum ScalarSlot : int {
+    SC_GAMMA = 0,   // ||r||^2
+    SC_PP,          // ||p||^2
+    SC_PQ,          // <p, H p>
+    SC_ALPHA,
+    SC_BETA,
+    SC_BNORM,       // ||b||
+    SC_REL,         // ||r|| / ||b||
+    SC_TRUE,        // true relative residual
+    SC_COUNT
+};
+enum IScalarSlot : int { IS_ACTIVE = 0, IS_ITERS, IS_STATUS, IS_COUNT };
+// global solve constants live in consts[]: [0] = 1/sigma^2, [1] = tol, [2] = max_iter
+
+struct msf_plan {
+    // geometry (host copy)
+    int nx = 0, ny = 0, nz = 0, nf = 0, nu = 0, nv = 0;
+    double du = 0, dv = 0, rs = 0, rsd = 0, offu = 0, offv = 0;
+    std::vector<int64_t> view_offset;
+    std::vector<double> angles;
+    int64_t n_views = 0, nvox = 0, nvox_total = 0, nmeas_total = 0;
+    int iv_lo = 0, iv_hi = -1;
+    msf_tiles tiles{};
+    std::vector<int64_t> tile_offset;     // host copy of the projector tile prefix
+    int64_t vol_blocks_per_frame = 0;     // blocks of the volume kernels per frame
+
+    // device tables
+    double2 *d_cs = nullptr;
+    int64_t *d_view_offset = nullptr;
+    int64_t *d_tile_offset = nullptr;
+
+    // device workspace
+    float *x = nullptr, *r = nullptr, *p = nullptr, *vin = nullptr;
+    double *bp = nullptr;         // backprojection accumulator (FP64 atomic adds)
+    float *sy = nullptr, *slam = nullptr, *sz = nullptr;
+    double *part_proj = nullptr;  // [total_tiles]
+    double *part_vol = nullptr;   // [nf * vol_blocks_per_frame]
+    double *scal = nullptr;       // [SC_COUNT][nf]
+    int32_t *iscal = nullptr;     // [IS_COUNT][nf]
+    double *consts = nullptr;     // [4]
+    int32_t *flags = nullptr;     // [4] validation counters
+    void *host_stage = nullptr;   // pinned host staging
+    size_t host_stage_bytes = 0;
+    int64_t workspace_bytes = 0;
+
+    // captured CG steps (one graph = graph_steps CG steps)
+    hipGraphExec_t graph = nullptr;
+    bool graph_valid = false;
+    int graph_steps = 0;
+    bool graph_timing = false;
+
+    // live kernel timing with HIP events (msf_plan_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;        // 4 per CG step of a check period
+    double t_fwd_ms = 0.0, t_back_ms = 0.0;
+    int64_t n_fwd = 0, n_back = 0;
+
+    ProjParams proj_params(bool with_active) const;
+    int64_t total_tiles() const { return tile_offset.empty() ? 0 : tile_offset.back(); }
+};
+
+// error reporting (thread-local message)
+void set_error(const std::string &msg);
+msf_status hip_fail(hipError_t e, const char *where);
+
+// ------------------------------------------------------------ launchers --
+hipError_t launch_forward(const msf_plan &P, int mode, const float *vol, const float *y, float *out,
+                          bool with_active, hipStream_t s);
+hipError_t launch_back_scatter(const msf_plan &P, const float *sino, double *vol_acc, bool with_active,
+                               hipStream_t s);
+hipError_t launch_back_gather(const msf_plan &P, const float *sino, float *vol_out, bool with_active,
+                              hipStream_t s);
+
+// batched transpose [B][R][C] -> [B][C][R]; counts entries failing the check
+// into flags[check_slot] (check: 0 none, 1 non-finite, 2 negative or non-finite)
+hipError_t launch_transpose(const float *in, float *out, int64_t B, int R, int C, int check, int32_t *flags,
+                            hipStream_t s);
+
+// CG vector / scalar kernels (see cg.hip)
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_d(double *p, int64_t n, hipStream_t s);
+hipError_t launch_d2f(const double *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
+hipError_t launch_sino_mul(const float *a, const float *b, float *out, int64_t n, hipStream_t s);
+hipError_t launch_vol_bnorm(msf_plan &P, hipStream_t s);
+hipError_t launch_vol_init_residual(msf_plan &P, hipStream_t s);
+hipError_t launch_vol_true_residual(msf_plan &P, hipStream_t s);
+hipError_t launch_scalar_reduce(msf_plan &P, int what, hipStream_t s);
+// ev: 4 events (forward start/stop, backprojection start/stop) or nullptr
+hipError_t launch_cg_step(msf_plan &P, hipStream_t s, hipEvent_t *ev);
+
+enum ReduceWhat : int {
+    RW_BNORM = 0,      // part_vol -> SC_BNORM
+    RW_INIT = 1,       // part_vol -> SC_GAMMA, SC_PP = SC_GAMMA, active flags
+    RW_TRUE = 2,       // part_vol -> SC_TRUE
+};

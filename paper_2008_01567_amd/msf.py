@@ -1,0 +1,227 @@
+"""Python binding of libmsf.so (argument marshalling only).
+
+Every step of the computation runs in the HIP library; this module turns
+torch tensors into device pointers and the current HIP stream, and C status
+codes into exceptions.  The names follow include/msf.h.
+
+If ``libmsf.so`` has not been built, importing works but every call raises:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsf.so")
+
+MSF_OK, MSF_NOT_CONVERGED, MSF_CNN_FALLBACK = 0, 1, 2
+MSF_EINVAL, MSF_ENOMEM, MSF_EHIP, MSF_EBREAKDOWN = -1, -2, -3, -4
+MSF_X0_V, MSF_X0_USER, MSF_X0_CNN = 0, 1, 2
+STATUS_NAMES = {0: "MSF_OK", 1: "MSF_NOT_CONVERGED", 2: "MSF_CNN_FALLBACK", -1: "MSF_EINVAL",
+                -2: "MSF_ENOMEM", -3: "MSF_EHIP", -4: "MSF_EBREAKDOWN"}
+
+
+class MsfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class msf_geometry(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("n_frames", C.c_int32),
+                ("nu", C.c_int32), ("nv", C.c_int32), ("du", C.c_double), ("dv", C.c_double),
+                ("src_iso", C.c_double), ("src_det", C.c_double), ("det_off_u", C.c_double),
+                ("det_off_v", C.c_double), ("view_offset", C.POINTER(C.c_int64)),
+                ("angles", C.POINTER(C.c_double))]
+
+
+class msf_tiles(C.Structure):
+    _fields_ = [("rays_per_lane", C.c_int32), ("waves_per_group", C.c_int32), ("back_mode", C.c_int32),
+                ("xcd_remap", C.c_int32)]
+
+
+class msf_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
+                ("x0_mode", C.c_int32), ("use_graph", C.c_int32), ("true_residual", C.c_int32),
+                ("reserved", C.c_int32), ("x0", C.c_void_p), ("cnn", C.c_void_p)]
+
+
+class msf_solve_stats(C.Structure):
+    _fields_ = [("iters", C.POINTER(C.c_int32)), ("rel_residual", C.POINTER(C.c_double)),
+                ("true_rel_residual", C.POINTER(C.c_double)), ("converged", C.POINTER(C.c_uint8)),
+                ("cnn_used", C.POINTER(C.c_uint8)), ("steps", C.c_int32), ("reserved", C.c_int32),
+                ("seconds", C.c_double)]
+
+
+class msf_timing(C.Structure):
+    _fields_ = [("forward_ms", C.c_double), ("forward_launches", C.c_int64), ("back_ms", C.c_double),
+                ("back_launches", C.c_int64)]
+
+
+_lib = None
+
+# every symbol the header declares (checked by the ABI test)
+EXPORTS = ["msf_solve_opts_default", "msf_plan_create", "msf_plan_destroy", "msf_plan_set_tiles",
+           "msf_plan_get_tiles", "msf_plan_sizes", "msf_project", "msf_backproject", "msf_prox_solve",
+           "msf_last_error", "msf_version", "msf_plan_set_timing", "msf_plan_get_timing",
+           "msf_count_intersections"]
+
+
+def lib():
+    """Load libmsf.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmsf.so is not built (python -m paper_2008_01567_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.msf_last_error.restype = C.c_char_p
+        L.msf_version.restype = C.c_char_p
+        L.msf_solve_opts_default.argtypes = [C.POINTER(msf_solve_opts)]
+        L.msf_plan_create.argtypes = [C.POINTER(msf_geometry), C.POINTER(vp)]
+        L.msf_plan_destroy.argtypes = [vp]
+        L.msf_plan_set_tiles.argtypes = [vp, C.POINTER(msf_tiles)]
+        L.msf_plan_get_tiles.argtypes = [vp, C.POINTER(msf_tiles)]
+        L.msf_plan_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.msf_project.argtypes = [vp, vp, vp, vp]
+        L.msf_backproject.argtypes = [vp, vp, vp, vp]
+        L.msf_prox_solve.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(msf_solve_opts), vp,
+                                     C.POINTER(msf_solve_stats), vp]
+        L.msf_plan_set_timing.argtypes = [vp, C.c_int32]
+        L.msf_plan_get_timing.argtypes = [vp, C.POINTER(msf_timing)]
+        L.msf_count_intersections.argtypes = [vp, C.POINTER(C.c_int64), vp]
+        for name in EXPORTS:
+            if name not in ("msf_last_error", "msf_version", "msf_plan_destroy", "msf_solve_opts_default"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().msf_last_error().decode()
+
+
+def _check(status):
+    if status < 0:
+        raise MsfError(status, last_error())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 device tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError("expected %d elements, got %d" % (numel, t.numel()))
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan for one scan geometry (``geom`` has the fields of msf_geometry;
+    ``paper_2008_01567_amd.synth.Geometry`` works)."""
+
+    def __init__(self, geom):
+        self._vo = np.ascontiguousarray(geom.view_offset, dtype=np.int64)
+        self._an = np.ascontiguousarray(geom.angles, dtype=np.float64)
+        g = msf_geometry(geom.nx, geom.ny, geom.nz, geom.n_frames, geom.nu, geom.nv, geom.du, geom.dv,
+                         geom.src_iso, geom.src_det, geom.det_off_u, geom.det_off_v,
+                         self._vo.ctypes.data_as(C.POINTER(C.c_int64)),
+                         self._an.ctypes.data_as(C.POINTER(C.c_double)))
+        h = C.c_void_p()
+        _check(lib().msf_plan_create(C.byref(g), C.byref(h)))
+        self._h = h
+        self.geom = geom
+        self.vol_shape = (geom.n_frames, geom.nz, geom.ny, geom.nx)
+        self.n_vox = geom.n_frames * geom.nz * geom.ny * geom.nx
+        self.n_meas = int(self._vo[-1]) * geom.nv * geom.nu
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().msf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tiles(self, rays_per_lane=2, waves_per_group=4, back_mode=0, xcd_remap=1):
+        t = msf_tiles(rays_per_lane, waves_per_group, back_mode, xcd_remap)
+        _check(lib().msf_plan_set_tiles(self._h, C.byref(t)))
+
+    def get_tiles(self) -> dict:
+        t = msf_tiles()
+        _check(lib().msf_plan_get_tiles(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in msf_tiles._fields_}
+
+    def sizes(self) -> dict:
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().msf_plan_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"n_vox": a.value, "n_meas": b.value, "workspace_bytes": c.value}
+
+    def set_timing(self, enable=True):
+        _check(lib().msf_plan_set_timing(self._h, int(bool(enable))))
+
+    def get_timing(self) -> dict:
+        t = msf_timing()
+        _check(lib().msf_plan_get_timing(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in msf_timing._fields_}
+
+    def count_intersections(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.geom.n_frames, dtype=np.int64)
+        _check(lib().msf_count_intersections(self._h, out.ctypes.data_as(C.POINTER(C.c_int64)), _stream(stream)))
+        return out
+
+    def project(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty(self.n_meas, dtype=torch.float32, device=x.device)
+        _check(lib().msf_project(self._h, _ptr(x, self.n_vox), _ptr(y, self.n_meas), _stream(stream)))
+        return y
+
+    def backproject(self, y, x=None, stream=None):
+        import torch
+        if x is None:
+            x = torch.empty(self.vol_shape, dtype=torch.float32, device=y.device)
+        _check(lib().msf_backproject(self._h, _ptr(y, self.n_meas), _ptr(x, self.n_vox), _stream(stream)))
+        return x
+
+    def prox_solve(self, v, y, lam, sigma, tol=1e-6, max_iter=1000, check_every=8, x0=None, use_graph=True,
+                   true_residual=False, out=None, stream=None):
+        """Returns (x, stats) with stats a dict of per-frame arrays and the status code."""
+        import torch
+        nf = self.geom.n_frames
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=torch.float32, device=v.device)
+        o = msf_solve_opts()
+        lib().msf_solve_opts_default(C.byref(o))
+        o.tol, o.max_iter, o.check_every = float(tol), int(max_iter), int(check_every)
+        o.use_graph, o.true_residual = int(bool(use_graph)), int(bool(true_residual))
+        if x0 is not None:
+            o.x0_mode = MSF_X0_USER
+            o.x0 = _ptr(x0, self.n_vox).value
+        iters = np.zeros(nf, dtype=np.int32)
+        rel = np.zeros(nf)
+        trel = np.zeros(nf)
+        conv = np.zeros(nf, dtype=np.uint8)
+        used = np.zeros(nf, dtype=np.uint8)
+        st = msf_solve_stats(iters.ctypes.data_as(C.POINTER(C.c_int32)), rel.ctypes.data_as(C.POINTER(C.c_double)),
+                             trel.ctypes.data_as(C.POINTER(C.c_double)), conv.ctypes.data_as(C.POINTER(C.c_uint8)),
+                             used.ctypes.data_as(C.POINTER(C.c_uint8)), 0, 0, 0.0)
+        status = _check(lib().msf_prox_solve(self._h, _ptr(v, self.n_vox), _ptr(y, self.n_meas),
+                                             _ptr(lam, self.n_meas), float(sigma), C.byref(o),
+                                             _ptr(out, self.n_vox), C.byref(st), _stream(stream)))
+        return out, {"status": status, "iters": iters, "rel_residual": rel, "true_rel_residual": trel,
+                     "converged": conv.astype(bool), "cnn_used": used.astype(bool), "steps": st.steps,
+                     "seconds": st.seconds}

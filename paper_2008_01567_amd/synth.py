@@ -307,11 +307,30 @@ def make_phantom(cfg: Config, frames=None, dtype=np.float64, shapes=None) -> np.
     frames = range(cfg.n_frames) if frames is None else list(frames)
     shapes = make_shapes(cfg) if shapes is None else shapes
     nx, ny, nz = cfg.n
-    out = np.zeros((len(frames), nz, ny, nx), dtype=np.float64)
+    out = np.zeros((len(frames), nz, ny, nx), dtype=dtype)
+    if cfg.moving:
+        for i, f in enumerate(frames):
+            vol = np.zeros((nz, ny, nx))
+            for s in shapes:
+                _render_shape(s, frame_centre(s, cfg, f), cfg.n, cfg.supersample, vol)
+            out[i] = vol
+        return out
+    # rigid +1 voxel / frame motion along z: render the scene once on a z-extended
+    # grid and cut every frame out of it (frame f sees the scene shifted by d_f)
+    d = [f - cfg.n_frames // 2 for f in range(cfg.n_frames)]
+    dmin, dmax = min(d), max(d)
+    ne = nz + dmax - dmin
+    ext = np.zeros((ne, ny, nx))
+    # frame f, slice k  <->  extended slice e = k - d_f + dmax; in the extended
+    # grid's own centred coordinates the scene sits (dmax + dmin)/2 higher
+    shift = (dmax + dmin) / 2.0
+    for s in shapes:
+        c = s.centre + np.array([0.0, 0.0, shift])
+        _render_shape(s, c, (nx, ny, ne), cfg.supersample, ext)
     for i, f in enumerate(frames):
-        for s in shapes:
-            _render_shape(s, frame_centre(s, cfg, f), cfg.n, cfg.supersample, out[i])
-    return out.astype(dtype, copy=False)
+        lo = dmax - d[f]
+        out[i] = ext[lo:lo + nz]
+    return out
 
 
 def make_v(cfg: Config, x0: np.ndarray, frames=None, std: float = 0.002) -> np.ndarray:

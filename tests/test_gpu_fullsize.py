@@ -1,0 +1,82 @@
+"""Parity at the benchmark's full size (128^3 x 16 frames, 192^2 detector,
+16 views per frame), in the launch configuration bench.py times: the whole
+batch runs on the GPU; the FP64 oracle checks sampled frames completely and
+sampled rays / voxels of the others."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_01567_amd import synth
+from _problems import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FRAMES = (0, 11)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_01567_amd import msf
+    cfg = synth.config("c2")
+    g = synth.make_geometry(cfg)
+    x0 = synth.make_phantom(cfg).astype(np.float32).astype(np.float64)
+    v = synth.make_v(cfg, x0).astype(np.float32).astype(np.float64)
+    mats = {f: oracle.FrameMatrix(g.subset([f]), 0) for f in FRAMES}
+    # measurement of every frame from the oracle projector (frames not in FRAMES too)
+    y, lam = oracle.make_measurement(cfg, g, x0)
+    y = y.astype(np.float32).astype(np.float64)
+    lam = lam.astype(np.float32).astype(np.float64)
+    plan = msf.Plan(g)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    return msf, cfg, g, x0, v, y, lam, mats, plan, dev
+
+
+def test_fullsize_projection_and_nnz(setup):
+    msf, cfg, g, x0, v, y, lam, mats, plan, dev = setup
+    got = plan.project(dev(x0)).cpu().numpy()
+    for f in FRAMES:
+        want = mats[f].A(x0[f])
+        assert rel_l2(got[g.sino_slice(f)], want) <= 2e-6
+    # sampled rays of every frame
+    rng = np.random.default_rng(0)
+    for f in range(g.n_frames):
+        vw = rng.integers(0, g.views_of(f), 64)
+        iv = rng.integers(40, 152, 64)
+        iu = rng.integers(20, 172, 64)
+        want = oracle.project_rays(g, f, vw, iv, iu, x0[f])
+        idx = g.sino_slice(f).start + (vw * g.nv + iv) * g.nu + iu
+        assert np.allclose(got[idx], want, rtol=2e-5, atol=1e-6 * want.max())
+    # the GPU traversal finds the oracle's intersections, except pieces shorter than
+    # the FP32 spacing of its crossing parameters (~1e-5 voxel), which it merges
+    nnz = plan.count_intersections()
+    for f in FRAMES:
+        assert 0 <= mats[f].nnz - int(nnz[f]) <= 1e-3 * mats[f].nnz
+
+
+def test_fullsize_backprojection(setup):
+    msf, cfg, g, x0, v, y, lam, mats, plan, dev = setup
+    z = lam * y
+    got = plan.backproject(dev(z)).cpu().numpy()
+    for f in FRAMES:
+        assert rel_l2(got[f], mats[f].AT(z[g.sino_slice(f)]).reshape(got[f].shape)) <= 2e-6
+
+
+def test_fullsize_prox_parity(setup):
+    """The batched solve at the frozen stopping rule meets 1e-4 relative error."""
+    msf, cfg, g, x0, v, y, lam, mats, plan, dev = setup
+    x, st = plan.prox_solve(dev(v), dev(y), dev(lam), cfg.sigma, tol=1e-6, max_iter=6000, check_every=16,
+                            true_residual=True)
+    x = x.cpu().numpy()
+    print("iters", st["iters"].tolist(), "true", st["true_rel_residual"].tolist(), flush=True)
+    assert st["status"] == msf.MSF_OK
+    for f in FRAMES:
+        s = g.sino_slice(f)
+        xs, ost = mats[f].prox_cg(v[f], y[s], lam[s], cfg.sigma, tol=1e-11, max_iter=20000)
+        err = rel_l2(x[f], xs)
+        print("frame", f, "oracle iters", ost["iters"], "err", err, flush=True)
+        assert err <= 1e-4
+    # every frame: optimality of the result, measured with the oracle's FP64 operator on sampled frames
+    assert (st["true_rel_residual"] <= 1e-5).all()
