@@ -84,9 +84,9 @@ typedef struct msf_cnn msf_cnn;
 
 /* Kernel launch shapes (chosen by the autotuner, or defaults). */
 typedef struct msf_tiles {
-    int32_t rays_per_lane;       /* forward/back projector: rays of one detector column per lane: 1, 2 or 4 */
+    int32_t rays_per_lane;       /* rays of one detector column per lane: 1, 2, 3, 4 or 6 */
     int32_t waves_per_group;     /* projector workgroup size in 64-lane waves: 1, 2 or 4 */
-    int32_t back_mode;           /* 0 = ray-driven scatter (atomic adds), 1 = voxel-driven gather */
+    int32_t back_mode;           /* 0 = ray-driven scatter (FP64 atomic adds), 1 = voxel-driven gather (default) */
     int32_t xcd_remap;           /* 1 = keep a frame's tiles on one XCD (L2 locality) */
 } msf_tiles;
 

@@ -29,7 +29,7 @@ void free_plan_memory(msf_plan *P)
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     P->graph = nullptr;
     P->graph_valid = false;
-    void *ptrs[] = {P->d_cs, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
+    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
                     P->sy, P->slam, P->sz, P->part_proj, P->part_vol, P->scal, P->iscal, P->consts,
                     P->flags};
     for (void *q : ptrs)
@@ -65,6 +65,21 @@ void row_range(msf_plan &P)
         P.iv_lo = lo;
         P.iv_hi = hi;
     }
+    // |dz/ds| = |v| / L_xy <= |v| / src_det; a piece inside one xy cell is at most
+    // sqrt(2) long in s, so below this slope it crosses at most one z plane
+    const double vmax = std::max(std::fabs((P.iv_lo - 0.5 * (P.nv - 1)) * P.dv + P.offv),
+                                 std::fabs((P.iv_hi - 0.5 * (P.nv - 1)) * P.dv + P.offv));
+    P.steep = vmax / P.rsd * std::sqrt(2.0) >= 0.999;
+}
+
+// Rays per lane: one wave covers all rows of a detector column that can meet
+// the volume, in as few 64-row passes as possible.
+int default_rays_per_lane(const msf_plan &P)
+{
+    const int rows = P.iv_hi - P.iv_lo + 1;
+    const int need = (rows + 63) / 64;
+    if (need <= 4) return std::max(need, 1);
+    return 6;
 }
 
 msf_status setup_tiles(msf_plan &P)
@@ -98,9 +113,10 @@ msf_status setup_tiles(msf_plan &P)
 
 bool tiles_ok(const msf_tiles &t)
 {
-    return (t.rays_per_lane == 1 || t.rays_per_lane == 2 || t.rays_per_lane == 4) &&
+    return (t.rays_per_lane == 1 || t.rays_per_lane == 2 || t.rays_per_lane == 3 || t.rays_per_lane == 4 ||
+            t.rays_per_lane == 6) &&
            (t.waves_per_group == 1 || t.waves_per_group == 2 || t.waves_per_group == 4) &&
-           (t.back_mode == 0) && (t.xcd_remap == 0 || t.xcd_remap == 1);
+           (t.back_mode == 0 || t.back_mode == 1) && (t.xcd_remap == 0 || t.xcd_remap == 1);
 }
 
 #define HIPCHK(expr)                                         \
@@ -194,11 +210,11 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
     P->nvox_total = P->nvox * g->n_frames;
     P->nmeas_total = nviews * (int64_t)g->nu * g->nv;
     P->vol_blocks_per_frame = (P->nvox + vol_chunk() - 1) / vol_chunk();
-    P->tiles.rays_per_lane = 2;
-    P->tiles.waves_per_group = 4;
-    P->tiles.back_mode = 0;
-    P->tiles.xcd_remap = 1;
     row_range(*P);
+    P->tiles.rays_per_lane = default_rays_per_lane(*P);
+    P->tiles.waves_per_group = 4;
+    P->tiles.back_mode = 1;
+    P->tiles.xcd_remap = 1;
 
     auto fail = [&](msf_status st) { free_plan_memory(P); delete P; return st; };
     hipError_t e;
@@ -207,6 +223,16 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
     for (int64_t i = 0; i < nviews; ++i) cs[i] = make_double2(std::cos(P->angles[i]), std::sin(P->angles[i]));
     if ((e = dalloc(&P->d_cs, (size_t)std::max<int64_t>(nviews, 1), tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
     if ((e = dalloc(&P->d_view_offset, P->nf + 1, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->d_rzp, (size_t)P->nv, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->d_cols, (size_t)std::max<int64_t>(nviews * P->nu, 1), tot)) != hipSuccess)
+        return fail(hip_fail(e, "hipMalloc"));
+    std::vector<double2> rzp(P->nv);
+    for (int iv = 0; iv < P->nv; ++iv) {
+        const double zp = (iv - 0.5 * (P->nv - 1)) * P->dv + P->offv;
+        rzp[iv] = make_double2(zp, zp != 0.0 ? 1.0 / zp : 0.0);
+    }
+    if ((e = hipMemcpy(P->d_rzp, rzp.data(), sizeof(double2) * P->nv, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(hip_fail(e, "hipMemcpy"));
     float **vols[] = {&P->x, &P->r, &P->p, &P->vin};
     for (float **v : vols)
         if ((e = dalloc(v, (size_t)P->nvox_total, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc volume"));
@@ -234,6 +260,7 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
         return fail(hip_fail(e, "hipMemset"));
     msf_status st = setup_tiles(*P);
     if (st != MSF_OK) return fail(st);
+    if ((e = launch_col_table(*P, nullptr)) != hipSuccess) return fail(hip_fail(e, "column table"));
     if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(hip_fail(e, "hipDeviceSynchronize"));
     *out = P;
     return MSF_OK;
@@ -286,6 +313,8 @@ msf_status msf_project(msf_plan *P, const float *x, float *y, void *stream)
     if (!P || !x || !y) { set_error("null argument"); return MSF_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(vol_to_internal(*P, x, P->p, 0, nullptr, s));
+    // rows that cannot meet the volume are not traced: they must read as zero
+    HIPCHK(launch_fill(P->sz, P->nmeas_total, 0.0f, s));
     HIPCHK(launch_forward(*P, PM_PLAIN, P->p, nullptr, P->sz, false, s));
     HIPCHK(sino_to_public(*P, P->sz, y, s));
     return MSF_OK;
@@ -298,7 +327,7 @@ msf_status msf_backproject(msf_plan *P, const float *y, float *x, void *stream)
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(sino_to_internal(*P, y, P->sz, 0, nullptr, s));
     HIPCHK(launch_fill_d(P->bp, P->nvox_total, s));
-    HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
     HIPCHK(launch_d2f(P->bp, P->p, P->nvox_total, s));
     HIPCHK(vol_to_public(*P, P->p, x, s));
     HIPCHK(launch_fill_d(P->bp, P->nvox_total, s));
@@ -388,12 +417,12 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
 
     // ||b|| with b = A^T Lambda y + v / sigma^2
     HIPCHK(launch_sino_mul(P->slam, P->sy, P->sz, P->nmeas_total, s));
-    HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
     HIPCHK(launch_vol_bnorm(*P, s));
     HIPCHK(launch_scalar_reduce(*P, RW_BNORM, s));
     // r = b - H x0, p = r
     HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
-    HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
     HIPCHK(launch_vol_init_residual(*P, s));
     HIPCHK(launch_scalar_reduce(*P, RW_INIT, s));
 
@@ -465,7 +494,7 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
     HIPCHK(vol_to_public(*P, P->x, x_out, s));
     if (o.true_residual) {
         HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
-        HIPCHK(launch_back_scatter(*P, P->sz, P->bp, false, s));
+        HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
         HIPCHK(launch_vol_true_residual(*P, s));
         HIPCHK(launch_scalar_reduce(*P, RW_TRUE, s));
     }

@@ -399,7 +399,7 @@ hipError_t launch_cg_step(msf_plan &P, hipStream_t s, hipEvent_t *ev)
     hipLaunchKernelGGL(k_red_alpha, dim3(P.nf), dim3(VB), 0, s, scal_args(P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecordWithFlags(ev[2], s, hipEventRecordExternal)) != hipSuccess) return e;
-    if ((e = launch_back_scatter(P, P.sz, P.bp, true, s)) != hipSuccess) return e;
+    if ((e = launch_back(P, P.sz, P.bp, true, s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecordWithFlags(ev[3], s, hipEventRecordExternal)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_update_xr, vol_grid(P), dim3(VB), 0, s, vol_args(P, true));
     if ((e = hipGetLastError()) != hipSuccess) return e;

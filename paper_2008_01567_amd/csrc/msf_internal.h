@@ -41,6 +41,21 @@ struct ProjParams {
     int xcd_remap;
     int64_t nvox;                // voxels per frame
     int64_t total_tiles;
+    const double2 *rzp;          // [nv] (height zp of detector row v, 1/zp or 0 when zp = 0)
+    // voxel-driven backprojector
+    const struct ColEntry *cols; // [n_views * nu] column table
+    int64_t g_tiles_per_frame;
+    int g_zpl;                   // z voxels per lane
+};
+
+// One detector column's xy line (shared by all its rows), as the forward
+// projector computes it; the voxel-driven backprojector reads it from a table
+// so both use identical plane-crossing parameters.
+struct ColEntry {
+    double iex, iey, cx, cy;     // x/y plane k is crossed at s = k * iex + cx (resp. y)
+    double sf, lxy, inv_lxy;     // source -> foot point, source -> pixel (xy), its inverse
+    double s_in, s_out;          // xy-box clip
+    int32_t hit, ixf, iyf, pad;  // hit flag; fixed cell index of an axis with zero direction component
 };
 
 // Per-frame scalars of the batched CG (device, FP64).
@@ -66,12 +81,15 @@ struct msf_plan {
     std::vector<double> angles;
     int64_t n_views = 0, nvox = 0, nvox_total = 0, nmeas_total = 0;
     int iv_lo = 0, iv_hi = -1;
+    bool steep = false;                   // some ray may cross two z planes inside one xy cell
     msf_tiles tiles{};
     std::vector<int64_t> tile_offset;     // host copy of the projector tile prefix
     int64_t vol_blocks_per_frame = 0;     // blocks of the volume kernels per frame
 
     // device tables
     double2 *d_cs = nullptr;
+    double2 *d_rzp = nullptr;             // [nv]
+    ColEntry *d_cols = nullptr;           // [n_views * nu]
     int64_t *d_view_offset = nullptr;
     int64_t *d_tile_offset = nullptr;
 
@@ -114,8 +132,12 @@ hipError_t launch_forward(const msf_plan &P, int mode, const float *vol, const f
                           bool with_active, hipStream_t s);
 hipError_t launch_back_scatter(const msf_plan &P, const float *sino, double *vol_acc, bool with_active,
                                hipStream_t s);
-hipError_t launch_back_gather(const msf_plan &P, const float *sino, float *vol_out, bool with_active,
+hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_out, bool with_active,
                               hipStream_t s);
+// A^T into the FP64 accumulator with the plan's back_mode (scatter adds into a
+// zeroed buffer; gather overwrites every voxel of the frames it processes)
+hipError_t launch_back(const msf_plan &P, const float *sino, double *vol, bool with_active, hipStream_t s);
+hipError_t launch_col_table(msf_plan &P, hipStream_t s);
 
 // batched transpose [B][R][C] -> [B][C][R]; counts entries failing the check
 // into flags[check_slot] (check: 0 none, 1 non-finite, 2 negative or non-finite)

@@ -36,18 +36,45 @@
 namespace {
 
 constexpr int WAVE = 64;
+constexpr int FLUSH = 16;   // cells per FP32 partial sum before it is added to the FP64 ray sum
+
+// Parameter of the crossing with plane k of an axis: s = k * inv + c0, with
+// inv = 1/e (direction component) and c0 = (-half - f) * inv.  Every kernel
+// computes crossings with this one expression, so A and A^T see the same
+// rounded values.
+__device__ __forceinline__ double plane_s(int k, double inv, double c0) { return fma((double)k, inv, c0); }
 
 struct Column {
-    double fx, fy;      // foot point of the xy line (closest approach to the z axis)
-    double ex, ey;      // unit xy direction, source -> pixel
-    double iex, iey;    // 1/ex, 1/ey (unused when the component is 0)
+    double iex, iey;    // 1/ex, 1/ey (0 when the component is 0)
+    double cx, cy;      // crossing offsets (see plane_s)
     double sf;          // xy distance source -> foot point (the source sits at s = -sf)
-    double inv_lxy;     // 1 / (xy distance source -> pixel)
+    double lxy;         // xy distance source -> pixel
+    double inv_lxy;
     double s_in, s_out; // xy-box clip of the line
     int ix, iy;         // entry cell
     int stepx, stepy;
     double sxn, syn;    // next x / y plane crossing
 };
+
+// Axis helper: range of s inside [0, n] planes, or false if the line misses.
+__device__ __forceinline__ bool axis_range(double e, double f, double h, int n, double &inv, double &c0,
+                                           double &s0, double &s1)
+{
+    if (e != 0.0) {
+        inv = 1.0 / e;
+        c0 = (-h - f) * inv;
+        const double a = plane_s(0, inv, c0), b = plane_s(n, inv, c0);
+        s0 = fmin(a, b);
+        s1 = fmax(a, b);
+        return true;
+    }
+    inv = 0.0;
+    c0 = 0.0;
+    if (!(f >= -h && f < h)) return false;
+    s0 = -INFINITY;
+    s1 = INFINITY;
+    return true;
+}
 
 __device__ __forceinline__ bool column_setup(const ProjParams &P, int view, int iu, Column &c)
 {
@@ -56,57 +83,58 @@ __device__ __forceinline__ bool column_setup(const ProjParams &P, int view, int 
     const double sx = P.rs * cs.x, sy = P.rs * cs.y;
     const double dx = -P.rsd * cs.x - u * cs.y;
     const double dy = -P.rsd * cs.y + u * cs.x;
-    const double lxy = sqrt(dx * dx + dy * dy);
-    c.ex = dx / lxy;
-    c.ey = dy / lxy;
-    c.inv_lxy = 1.0 / lxy;
-    c.sf = -(sx * c.ex + sy * c.ey);
-    c.fx = sx + c.sf * c.ex;
-    c.fy = sy + c.sf * c.ey;
+    c.lxy = sqrt(dx * dx + dy * dy);
+    const double ex = dx / c.lxy, ey = dy / c.lxy;
+    c.inv_lxy = 1.0 / c.lxy;
+    c.sf = -(sx * ex + sy * ey);
+    const double fx = sx + c.sf * ex, fy = sy + c.sf * ey;
     const double hx = 0.5 * P.nx, hy = 0.5 * P.ny;
     double sx0, sx1, sy0, sy1;
-    if (c.ex != 0.0) {
-        c.iex = 1.0 / c.ex;
-        const double a = (-hx - c.fx) * c.iex, b = (hx - c.fx) * c.iex;
-        sx0 = fmin(a, b);
-        sx1 = fmax(a, b);
-    } else {
-        c.iex = 0.0;
-        if (!(c.fx >= -hx && c.fx < hx)) return false;
-        sx0 = -INFINITY;
-        sx1 = INFINITY;
-    }
-    if (c.ey != 0.0) {
-        c.iey = 1.0 / c.ey;
-        const double a = (-hy - c.fy) * c.iey, b = (hy - c.fy) * c.iey;
-        sy0 = fmin(a, b);
-        sy1 = fmax(a, b);
-    } else {
-        c.iey = 0.0;
-        if (!(c.fy >= -hy && c.fy < hy)) return false;
-        sy0 = -INFINITY;
-        sy1 = INFINITY;
-    }
+    if (!axis_range(ex, fx, hx, P.nx, c.iex, c.cx, sx0, sx1)) return false;
+    if (!axis_range(ey, fy, hy, P.ny, c.iey, c.cy, sy0, sy1)) return false;
     c.s_in = fmax(sx0, sy0);
     c.s_out = fmin(sx1, sy1);
     if (!(c.s_out > c.s_in)) return false;
-    c.stepx = c.ex > 0.0 ? 1 : (c.ex < 0.0 ? -1 : 0);
-    c.stepy = c.ey > 0.0 ? 1 : (c.ey < 0.0 ? -1 : 0);
+    c.stepx = ex > 0.0 ? 1 : (ex < 0.0 ? -1 : 0);
+    c.stepy = ey > 0.0 ? 1 : (ey < 0.0 ? -1 : 0);
     // entry cell: the entering axis from the direction, the other from the entry point
     if (sx0 >= sy0) c.ix = c.stepx > 0 ? 0 : P.nx - 1;
-    else c.ix = min(max((int)floor(c.fx + c.ex * c.s_in + hx), 0), P.nx - 1);
+    else c.ix = min(max((int)floor(fx + ex * c.s_in + hx), 0), P.nx - 1);
     if (sy0 >= sx0) c.iy = c.stepy > 0 ? 0 : P.ny - 1;
-    else c.iy = min(max((int)floor(c.fy + c.ey * c.s_in + hy), 0), P.ny - 1);
-    c.sxn = c.stepx > 0 ? ((c.ix + 1) - hx - c.fx) * c.iex
-          : (c.stepx < 0 ? (c.ix - hx - c.fx) * c.iex : INFINITY);
-    c.syn = c.stepy > 0 ? ((c.iy + 1) - hy - c.fy) * c.iey
-          : (c.stepy < 0 ? (c.iy - hy - c.fy) * c.iey : INFINITY);
+    else c.iy = min(max((int)floor(fy + ey * c.s_in + hy), 0), P.ny - 1);
+    c.sxn = c.stepx ? plane_s(c.ix + (c.stepx > 0), c.iex, c.cx) : INFINITY;
+    c.syn = c.stepy ? plane_s(c.iy + (c.stepy > 0), c.iey, c.cy) : INFINITY;
     return true;
+}
+
+// The walk is the same for the whole wave: keep its indices in scalar registers.
+__device__ __forceinline__ void make_uniform(Column &c)
+{
+    c.ix = __builtin_amdgcn_readfirstlane(c.ix);
+    c.iy = __builtin_amdgcn_readfirstlane(c.iy);
+    c.stepx = __builtin_amdgcn_readfirstlane(c.stepx);
+    c.stepy = __builtin_amdgcn_readfirstlane(c.stepy);
+}
+
+// 3D length per unit of s of the ray of detector row height zp (FP32, shared by A and A^T).
+__device__ __forceinline__ float ray_scale(double zp, double inv_lxy)
+{
+    const float mf = (float)(zp * inv_lxy);   // slope dz/ds
+    return sqrtf(fmaf(mf, mf, 1.0f));
+}
+
+// The ray of height zp on the detector (xy length lxy) is at height
+// z = zp (s + sf) / lxy; it crosses z plane k (z = k - nz/2) at
+//     s = (k - nz/2) * im - sf,   im = lxy / zp,
+// evaluated as fma(k - nz/2, im, -sf) by every kernel.
+__device__ __forceinline__ double zplane_s(int k, double hz, double im, double sf)
+{
+    return fma((double)k - hz, im, -sf);
 }
 
 // z-state of one ray (one detector row) along the shared xy line.
 struct RayZ {
-    double z0, im;      // z at the foot point; 1/m with m = dz/ds (0 if m == 0)
+    double im, sf;      // see zplane_s
     float lzi, lzo;     // s-range inside the z slab of the volume
     float szn;          // next z-plane crossing
     float scale;        // 3D length per unit s: sqrt(1 + m^2)
@@ -116,23 +144,24 @@ struct RayZ {
 __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, int iv, bool valid, RayZ &z)
 {
     const double hz = 0.5 * P.nz;
-    const double zp = (iv - 0.5 * (P.nv - 1)) * P.dv + P.offv;
-    const double m = zp * c.inv_lxy;
-    z.z0 = m * c.sf;
-    z.scale = (float)sqrt(1.0 + m * m);
+    const double2 zr = P.rzp[min(iv, P.nv - 1)];
+    const double zp = zr.x;
+    z.sf = c.sf;
+    z.scale = ray_scale(zp, c.inv_lxy);
     double lzi, lzo;
-    if (m != 0.0) {
-        z.im = 1.0 / m;
-        const double a = (-hz - z.z0) * z.im, b = (hz - z.z0) * z.im;
+    const double z_in = zp * (c.s_in + c.sf) * c.inv_lxy;   // height where the line enters the xy box
+    if (zp != 0.0) {
+        z.im = c.lxy * zr.y;
+        const double a = zplane_s(0, hz, z.im, c.sf), b = zplane_s(P.nz, hz, z.im, c.sf);
         lzi = fmin(a, b);
         lzo = fmax(a, b);
     } else {
         z.im = 0.0;
-        const bool in = z.z0 >= -hz && z.z0 < hz;
+        const bool in = z_in >= -hz && z_in < hz;
         lzi = in ? -INFINITY : INFINITY;
         lzo = in ? INFINITY : -INFINITY;
     }
-    z.zstep = m > 0.0 ? 1 : (m < 0.0 ? -1 : 0);
+    z.zstep = zp > 0.0 ? 1 : (zp < 0.0 ? -1 : 0);
     const double start = fmax(c.s_in, lzi);
     if (!valid || !(fmin(c.s_out, lzo) > start)) {
         z.lzi = INFINITY;
@@ -144,16 +173,47 @@ __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, 
     z.lzi = (float)lzi;
     z.lzo = (float)lzo;
     if (lzi >= c.s_in) z.iz = z.zstep > 0 ? 0 : P.nz - 1;
-    else z.iz = min(max((int)floor(z.z0 + m * c.s_in + hz), 0), P.nz - 1);
-    z.szn = z.zstep > 0 ? (float)(((z.iz + 1) - hz - z.z0) * z.im)
-          : (z.zstep < 0 ? (float)((z.iz - hz - z.z0) * z.im) : INFINITY);
+    else z.iz = min(max((int)floor(z_in + hz), 0), P.nz - 1);
+    z.szn = z.zstep ? (float)zplane_s(z.iz + (z.zstep > 0), hz, z.im, z.sf) : INFINITY;
 }
 
-// Walk the pieces of one ray inside the xy cell [a, b] of the current voxel
-// column, calling op(iz, length) for each z voxel with a positive length.
-template <class Op>
-__device__ __forceinline__ void ray_cell(RayZ &z, float scur, float snext, int nz, double hz, Op &&op)
+// One ray inside the xy cell [scur, snext] when at most one z plane can be
+// crossed per cell (|dz/ds| * sqrt(2) < 1, checked at plan creation): the
+// piece splits into (iz, l1) and (iz2, l2), l2 = 0 without a crossing.
+struct Pieces {
+    int iz, iz2;
+    float l1, l2;
+    bool cross;
+};
+
+__device__ __forceinline__ Pieces ray_pieces(const RayZ &z, float scur, float snext, int nz)
 {
+    Pieces q;
+    const float a = fmaxf(scur, z.lzi);
+    const float b = fminf(snext, z.lzo);
+    const bool on = b > a;
+    q.cross = on && z.szn < b;
+    const float mid = q.cross ? fmaxf(z.szn, a) : b;
+    q.l1 = on ? mid - a : 0.0f;
+    q.l2 = q.cross ? b - mid : 0.0f;
+    q.iz = z.iz;
+    q.iz2 = min(max(z.iz + (q.cross ? z.zstep : 0), 0), nz - 1);
+    return q;
+}
+
+__device__ __forceinline__ void ray_advance(RayZ &z, const Pieces &q, double hz)
+{
+    // branch-free: iz2 == iz without a crossing
+    const float nxt = (float)zplane_s(q.iz2 + (z.zstep > 0), hz, z.im, z.sf);
+    z.szn = q.cross ? nxt : z.szn;
+    z.iz = q.iz2;
+}
+
+// General case (steep rays): walk every z crossing inside the cell.
+template <class Op>
+__device__ __forceinline__ void ray_cell_general(RayZ &z, float scur, float snext, int nz, Op &&op)
+{
+    const double hz = 0.5 * nz;
     const float a = fmaxf(scur, z.lzi);
     const float b = fminf(snext, z.lzo);
     if (!(b > a)) return;
@@ -167,7 +227,7 @@ __device__ __forceinline__ void ray_cell(RayZ &z, float scur, float snext, int n
             z.lzo = -INFINITY;
             return;
         }
-        z.szn = (float)(((z.zstep > 0 ? z.iz + 1 : z.iz) - hz - z.z0) * z.im);
+        z.szn = (float)zplane_s(z.iz + (z.zstep > 0), hz, z.im, z.sf);
     }
     op(z.iz, b - sa);
 }
@@ -221,64 +281,108 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int R, int MODE>
+// Uniform 2D walk of the column's xy line; body(colp_offset, scur, snext)
+// is called once per xy cell, then flush() every FLUSH cells.
+template <class Body, class Flush>
+__device__ __forceinline__ void walk_xy(const ProjParams &P, const Column &c, Body &&body, Flush &&flush)
+{
+    float scur = (float)c.s_in;
+    int ix = c.ix, iy = c.iy;
+    double sxn = c.sxn, syn = c.syn;
+    int k = 0;
+    for (int guard = P.nx + P.ny + 2; guard > 0; --guard) {
+        const double s_next = fmin(fmin(sxn, syn), c.s_out);
+        const float snext = (float)s_next;
+        body((int64_t)(iy * P.nx + ix) * P.nz, scur, snext);
+        if (++k == FLUSH) {
+            flush();
+            k = 0;
+        }
+        if (s_next >= c.s_out) break;
+        if (sxn <= syn) {
+            ix += c.stepx;
+            if ((unsigned)ix >= (unsigned)P.nx) break;
+            sxn = plane_s(ix + (c.stepx > 0), c.iex, c.cx);
+        } else {
+            iy += c.stepy;
+            if ((unsigned)iy >= (unsigned)P.ny) break;
+            syn = plane_s(iy + (c.stepy > 0), c.iey, c.cy);
+        }
+        scur = snext;
+    }
+    flush();
+}
+
+template <int R, int MODE, bool STEEP>
 __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float *__restrict__ vol,
                                                  const float *__restrict__ lam, const float *__restrict__ y,
                                                  float *__restrict__ out, double *__restrict__ partial)
 {
     const int nwaves = blockDim.x / WAVE;
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x % WAVE;
     const int64_t t = logical_tile(blockIdx.x, gridDim.x, P.xcd_remap);
     const Tile T = decode_tile(P, t, wave, nwaves);
     double part = 0.0;
     if (T.ok) {
-        const double hz = 0.5 * P.nz;
-        const float hxf = 0.5f * P.nx, hyf = 0.5f * P.ny;
-        (void)hxf; (void)hyf;
         int iv[R];
-        double acc[R];   // FP64 ray sums: the FP32 x FP32 products are exact in FP64
+        double acc[R];   // FP64 ray sums, fed by FP32 partial sums of FLUSH cells
+        float acc32[R];
         RayZ z[R];
         Column c;
         const bool hit = column_setup(P, T.view, T.iu, c);
+        make_uniform(c);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             iv[r] = P.iv_lo + T.vc * P.rows_per_chunk + r * WAVE + lane;
             acc[r] = 0.0;
+            acc32[r] = 0.0f;
             if (hit) ray_setup(P, c, iv[r], iv[r] <= P.iv_hi, z[r]);
         }
         if (hit) {
             const float *volf = vol + (int64_t)T.frame * P.nvox;
-            const double hx = 0.5 * P.nx, hy = 0.5 * P.ny;
-            double s_cur = c.s_in;
-            float scur = (float)s_cur;
-            int ix = c.ix, iy = c.iy;
-            double sxn = c.sxn, syn = c.syn;
-            for (int guard = P.nx + P.ny + 2; guard > 0; --guard) {
-                const double s_next = fmin(fmin(sxn, syn), c.s_out);
-                const float snext = (float)s_next;
-                const float *colp = volf + (int64_t)(iy * P.nx + ix) * P.nz;
+            auto flush = [&]() {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    double a = acc[r];
-                    if (MODE == PM_COUNT)
-                        ray_cell(z[r], scur, snext, P.nz, hz, [&](int, float l) { a += l > 0.0f ? 1.0 : 0.0; });
-                    else
-                        ray_cell(z[r], scur, snext, P.nz, hz,
-                                 [&](int iz, float l) { a = fma((double)l, (double)colp[iz], a); });
-                    acc[r] = a;
+                    acc[r] += (double)acc32[r];
+                    acc32[r] = 0.0f;
                 }
-                if (s_next >= c.s_out) break;
-                if (sxn <= syn) {
-                    ix += c.stepx;
-                    if ((unsigned)ix >= (unsigned)P.nx) break;
-                    sxn = ((c.stepx > 0 ? ix + 1 : ix) - hx - c.fx) * c.iex;
-                } else {
-                    iy += c.stepy;
-                    if ((unsigned)iy >= (unsigned)P.ny) break;
-                    syn = ((c.stepy > 0 ? iy + 1 : iy) - hy - c.fy) * c.iey;
+            };
+            walk_xy(P, c, [&](int64_t off, float scur, float snext) {
+                const float *colp = volf + off;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (MODE == PM_COUNT) {
+                        if (STEEP) {
+                            ray_cell_general(z[r], scur, snext, P.nz, [&](int, float l) { acc32[r] += l > 0.0f; });
+                        } else {
+                            const Pieces q = ray_pieces(z[r], scur, snext, P.nz);
+                            acc32[r] += (float)(q.l1 > 0.0f) + (float)(q.l2 > 0.0f);
+                            ray_advance(z[r], q, 0.5 * P.nz);
+                        }
+                    } else if (STEEP) {
+                        ray_cell_general(z[r], scur, snext, P.nz,
+                                         [&](int iz, float l) { acc32[r] = fmaf(l, colp[iz], acc32[r]); });
+                    }
                 }
-                scur = snext;
-            }
+                if (MODE != PM_COUNT && !STEEP) {
+                    // all pieces first, then all 2R loads, then the sums: one wait per cell
+                    Pieces q[R];
+                    float p1[R], p2[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) q[r] = ray_pieces(z[r], scur, snext, P.nz);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        p1[r] = colp[(uint32_t)q[r].iz];
+                        p2[r] = colp[(uint32_t)q[r].iz2];
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        acc32[r] = fmaf(q[r].l2, p2[r], fmaf(q[r].l1, p1[r], acc32[r]));
+                        ray_advance(z[r], q[r], 0.5 * P.nz);
+                    }
+                }
+            }, flush);
         }
         const int64_t base = (int64_t)T.view * P.nu * P.nv + (int64_t)T.iu * P.nv;
 #pragma unroll
@@ -310,18 +414,19 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
     }
 }
 
-template <int R>
+template <int R, bool STEEP>
 __global__ __launch_bounds__(256) void k_back_scatter(const ProjParams P, const float *__restrict__ sino,
                                                       double *__restrict__ vol)
 {
     const int nwaves = blockDim.x / WAVE;
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x % WAVE;
     const int64_t t = logical_tile(blockIdx.x, gridDim.x, P.xcd_remap);
     const Tile T = decode_tile(P, t, wave, nwaves);
     if (!T.ok) return;
     Column c;
     if (!column_setup(P, T.view, T.iu, c)) return;
-    const double hz = 0.5 * P.nz;
+    make_uniform(c);
     RayZ z[R];
     float val[R];
     const int64_t base = (int64_t)T.view * P.nu * P.nv + (int64_t)T.iu * P.nv;
@@ -337,42 +442,176 @@ __global__ __launch_bounds__(256) void k_back_scatter(const ProjParams P, const 
         }
     }
     double *volf = vol + (int64_t)T.frame * P.nvox;
-    const double hx = 0.5 * P.nx, hy = 0.5 * P.ny;
-    float scur = (float)c.s_in;
-    int ix = c.ix, iy = c.iy;
-    double sxn = c.sxn, syn = c.syn;
-    for (int guard = P.nx + P.ny + 2; guard > 0; --guard) {
-        const double s_next = fmin(fmin(sxn, syn), c.s_out);
-        const float snext = (float)s_next;
-        double *colp = volf + (int64_t)(iy * P.nx + ix) * P.nz;
+    walk_xy(P, c, [&](int64_t off, float scur, float snext) {
+        double *colp = volf + off;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double v = val[r];
-            ray_cell(z[r], scur, snext, P.nz, hz, [&](int iz, float l) { unsafeAtomicAdd(colp + iz, (double)l * v); });
+            if (STEEP) {
+                ray_cell_general(z[r], scur, snext, P.nz,
+                                 [&](int iz, float l) { unsafeAtomicAdd(colp + iz, (double)l * v); });
+            } else {
+                const Pieces q = ray_pieces(z[r], scur, snext, P.nz);
+                if (q.l1 > 0.0f) unsafeAtomicAdd(colp + q.iz, (double)q.l1 * v);
+                if (q.l2 > 0.0f) unsafeAtomicAdd(colp + q.iz2, (double)q.l2 * v);
+                ray_advance(z[r], q, 0.5 * P.nz);
+            }
         }
-        if (s_next >= c.s_out) break;
-        if (sxn <= syn) {
-            ix += c.stepx;
-            if ((unsigned)ix >= (unsigned)P.nx) break;
-            sxn = ((c.stepx > 0 ? ix + 1 : ix) - hx - c.fx) * c.iex;
-        } else {
-            iy += c.stepy;
-            if ((unsigned)iy >= (unsigned)P.ny) break;
-            syn = ((c.stepy > 0 ? iy + 1 : iy) - hy - c.fy) * c.iey;
-        }
-        scur = snext;
-    }
+    }, [] {});
 }
 
-template <int R>
+
+__global__ void k_col_table(const ProjParams P, int64_t n_views, ColEntry *__restrict__ tab)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_views * P.nu) return;
+    Column c;
+    const bool hit = column_setup(P, (int)(i / P.nu), (int)(i % P.nu), c);
+    ColEntry e;
+    e.iex = c.iex; e.iey = c.iey; e.cx = c.cx; e.cy = c.cy;
+    e.sf = c.sf; e.lxy = c.lxy; e.inv_lxy = c.inv_lxy;
+    e.s_in = c.s_in; e.s_out = c.s_out;
+    e.hit = hit ? 1 : 0;
+    e.ixf = hit ? c.ix : 0;
+    e.iyf = hit ? c.iy : 0;
+    e.pad = 0;
+    tab[i] = e;
+}
+
+// Voxel-driven A^T.  One wave owns 64 * ZPL consecutive z voxels of one voxel
+// column (ix, iy) of one frame and loops over that frame's views.  For each
+// view the detector columns whose xy line meets the cell come from the
+// projections of the cell's four corners; for each of them (uniform) the
+// cell's piece [a, b] of the line uses the forward walk's crossing
+// expressions, and each lane finds the detector rows whose ray passes through
+// its voxel inside [a, b] and takes the piece length exactly as the forward
+// projector cuts it.  FP64 sums, one write per voxel, no atomics.
+template <int ZPL>
+__global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const float *__restrict__ sino,
+                                                     double *__restrict__ out)
+{
+    const int nwaves = blockDim.x / WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x % WAVE;
+    const int64_t t = logical_tile(blockIdx.x, gridDim.x, P.xcd_remap);
+    const int f = (int)(t / P.g_tiles_per_frame);
+    int64_t local = t - (int64_t)f * P.g_tiles_per_frame;
+    const int nxg = (P.nx + nwaves - 1) / nwaves;
+    const int xg = (int)(local % nxg);
+    local /= nxg;
+    const int iy = (int)(local % P.ny);
+    const int zc = (int)(local / P.ny);
+    const int ix = xg * nwaves + wave;
+    if (ix >= P.nx) return;
+    if (P.active && !P.active[f]) return;
+    const double hz = 0.5 * P.nz;
+    const float hzf = 0.5f * P.nz;
+    int iz[ZPL];
+    double acc[ZPL];
+#pragma unroll
+    for (int k = 0; k < ZPL; ++k) {
+        iz[k] = (zc * ZPL + k) * WAVE + lane;
+        acc[k] = 0.0;
+    }
+    const float x0 = ix - 0.5f * P.nx, y0 = iy - 0.5f * P.ny;
+    const float cu = 0.5f * (P.nu - 1), cv = 0.5f * (P.nv - 1);
+    const float rs = (float)P.rs, rsd = (float)P.rsd;
+    const float inv_du = (float)(1.0 / P.du), inv_dv = (float)(1.0 / P.dv);
+    const float offu = (float)P.offu, offv = (float)P.offv;
+    const int64_t v0 = P.view_offset[f], v1 = P.view_offset[f + 1];
+    for (int64_t v = v0; v < v1; ++v) {
+        const double2 cs = P.cs[v];
+        const float c = (float)cs.x, s = (float)cs.y;
+        float ulo = INFINITY, uhi = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float X = x0 + (q & 1), Y = y0 + (q >> 1);
+            const float b = Y * c - X * s;             // along e_u
+            const float a = rs - (X * c + Y * s);      // depth from the source (> 0)
+            const float fu = (rsd * b * __builtin_amdgcn_rcpf(a) - offu) * inv_du + cu;
+            ulo = fminf(ulo, fu);
+            uhi = fmaxf(uhi, fu);
+        }
+        const int iu0 = __builtin_amdgcn_readfirstlane(max((int)ceilf(ulo - 1e-3f), 0));
+        const int iu1 = __builtin_amdgcn_readfirstlane(min((int)floorf(uhi + 1e-3f), P.nu - 1));
+        float vacc[ZPL];
+#pragma unroll
+        for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
+        for (int iu = iu0; iu <= iu1; ++iu) {
+            const ColEntry &E = P.cols[v * P.nu + iu];
+            if (!E.hit) continue;
+            double xlo, xhi, ylo, yhi;
+            if (E.iex != 0.0) {
+                const double p0 = plane_s(ix, E.iex, E.cx), p1 = plane_s(ix + 1, E.iex, E.cx);
+                xlo = fmin(p0, p1);
+                xhi = fmax(p0, p1);
+            } else {
+                if (ix != E.ixf) continue;
+                xlo = -INFINITY;
+                xhi = INFINITY;
+            }
+            if (E.iey != 0.0) {
+                const double p0 = plane_s(iy, E.iey, E.cy), p1 = plane_s(iy + 1, E.iey, E.cy);
+                ylo = fmin(p0, p1);
+                yhi = fmax(p0, p1);
+            } else {
+                if (iy != E.iyf) continue;
+                ylo = -INFINITY;
+                yhi = INFINITY;
+            }
+            const double sa = fmax(fmax(xlo, ylo), E.s_in), sb = fmin(fmin(xhi, yhi), E.s_out);
+            const float fa = (float)sa, fb = (float)sb;
+            if (!(fb > fa)) continue;
+            // ray height z = zp (s + sf) / lxy: rows through [zlo, zhi] within [a, b]
+            const float lxyf = (float)E.lxy;
+            const float ka = lxyf * __builtin_amdgcn_rcpf((float)(sa + E.sf));
+            const float kb = lxyf * __builtin_amdgcn_rcpf((float)(sb + E.sf));
+            const float *srow = sino + (v * P.nu + iu) * (int64_t)P.nv;
+#pragma unroll
+            for (int k = 0; k < ZPL; ++k) {
+                const float zlo = iz[k] - hzf, zhi = zlo + 1.0f;
+                const float zp_lo = fminf(zlo * ka, zlo * kb), zp_hi = fmaxf(zhi * ka, zhi * kb);
+                const int iva = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
+                int ivb = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
+                if (iz[k] >= P.nz) ivb = iva - 1;
+                const double klo = (double)iz[k] - hz, khi = (double)(iz[k] + 1) - hz;
+                for (int ivr = iva; ivr <= ivb; ++ivr) {
+                    const double2 zr = P.rzp[ivr];
+                    float enter, exit;
+                    if (zr.x != 0.0) {
+                        const double im = E.lxy * zr.y;
+                        const float e1 = (float)fma(klo, im, -E.sf), e2 = (float)fma(khi, im, -E.sf);
+                        enter = fminf(e1, e2);
+                        exit = fmaxf(e1, e2);
+                    } else {
+                        const double z_in = zr.x * (E.s_in + E.sf) * E.inv_lxy;
+                        const bool in = z_in >= -hz && z_in < hz && min(max((int)floor(z_in + hz), 0), P.nz - 1) == iz[k];
+                        enter = in ? -INFINITY : INFINITY;
+                        exit = in ? INFINITY : -INFINITY;
+                    }
+                    const float l = fminf(fb, exit) - fmaxf(fa, enter);
+                    if (l > 0.0f) vacc[k] = fmaf(l * ray_scale(zr.x, E.inv_lxy), srow[ivr], vacc[k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
+    }
+    double *o = out + (int64_t)f * P.nvox + (int64_t)(iy * P.nx + ix) * P.nz;
+#pragma unroll
+    for (int k = 0; k < ZPL; ++k)
+        if (iz[k] < P.nz) o[iz[k]] = acc[k];
+}
+
+template <int R, bool STEEP>
 hipError_t fwd_dispatch_mode(const ProjParams &pp, int mode, dim3 grid, dim3 block, const float *vol,
                              const float *lam, const float *y, float *out, double *part, hipStream_t s)
 {
     switch (mode) {
-    case PM_PLAIN: hipLaunchKernelGGL((k_forward<R, PM_PLAIN>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
-    case PM_WEIGHTED: hipLaunchKernelGGL((k_forward<R, PM_WEIGHTED>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
-    case PM_COUNT: hipLaunchKernelGGL((k_forward<R, PM_COUNT>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
-    default: hipLaunchKernelGGL((k_forward<R, PM_RESID>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    case PM_PLAIN: hipLaunchKernelGGL((k_forward<R, PM_PLAIN, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    case PM_WEIGHTED: hipLaunchKernelGGL((k_forward<R, PM_WEIGHTED, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    case PM_COUNT: hipLaunchKernelGGL((k_forward<R, PM_COUNT, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    default: hipLaunchKernelGGL((k_forward<R, PM_RESID, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
     }
     return hipGetLastError();
 }
@@ -396,6 +635,11 @@ ProjParams msf_plan::proj_params(bool with_active) const
     pp.xcd_remap = tiles.xcd_remap;
     pp.nvox = nvox;
     pp.total_tiles = total_tiles();
+    pp.rzp = d_rzp;
+    pp.cols = d_cols;
+    pp.g_zpl = nz > 64 ? 2 : 1;
+    const int gw = tiles.waves_per_group;
+    pp.g_tiles_per_frame = (int64_t)((nx + gw - 1) / gw) * ny * ((nz + WAVE * pp.g_zpl - 1) / (WAVE * pp.g_zpl));
     return pp;
 }
 
@@ -405,10 +649,13 @@ hipError_t launch_forward(const msf_plan &P, int mode, const float *vol, const f
     const ProjParams pp = P.proj_params(with_active);
     if (pp.total_tiles == 0) return hipSuccess;
     const dim3 grid((unsigned)pp.total_tiles), block(WAVE * P.tiles.waves_per_group);
+    if (P.steep) return fwd_dispatch_mode<1, true>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
     switch (P.tiles.rays_per_lane) {
-    case 1: return fwd_dispatch_mode<1>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
-    case 2: return fwd_dispatch_mode<2>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
-    default: return fwd_dispatch_mode<4>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
+    case 1: return fwd_dispatch_mode<1, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
+    case 2: return fwd_dispatch_mode<2, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
+    case 3: return fwd_dispatch_mode<3, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
+    case 4: return fwd_dispatch_mode<4, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
+    default: return fwd_dispatch_mode<6, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
     }
 }
 
@@ -418,10 +665,43 @@ hipError_t launch_back_scatter(const msf_plan &P, const float *sino, double *vol
     const ProjParams pp = P.proj_params(with_active);
     if (pp.total_tiles == 0) return hipSuccess;
     const dim3 grid((unsigned)pp.total_tiles), block(WAVE * P.tiles.waves_per_group);
-    switch (P.tiles.rays_per_lane) {
-    case 1: hipLaunchKernelGGL((k_back_scatter<1>), grid, block, 0, s, pp, sino, vol_acc); break;
-    case 2: hipLaunchKernelGGL((k_back_scatter<2>), grid, block, 0, s, pp, sino, vol_acc); break;
-    default: hipLaunchKernelGGL((k_back_scatter<4>), grid, block, 0, s, pp, sino, vol_acc); break;
+    if (P.steep) {
+        hipLaunchKernelGGL((k_back_scatter<1, true>), grid, block, 0, s, pp, sino, vol_acc);
+        return hipGetLastError();
     }
+    switch (P.tiles.rays_per_lane) {
+    case 1: hipLaunchKernelGGL((k_back_scatter<1, false>), grid, block, 0, s, pp, sino, vol_acc); break;
+    case 2: hipLaunchKernelGGL((k_back_scatter<2, false>), grid, block, 0, s, pp, sino, vol_acc); break;
+    case 3: hipLaunchKernelGGL((k_back_scatter<3, false>), grid, block, 0, s, pp, sino, vol_acc); break;
+    case 4: hipLaunchKernelGGL((k_back_scatter<4, false>), grid, block, 0, s, pp, sino, vol_acc); break;
+    default: hipLaunchKernelGGL((k_back_scatter<6, false>), grid, block, 0, s, pp, sino, vol_acc); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_out, bool with_active,
+                              hipStream_t s)
+{
+    const ProjParams pp = P.proj_params(with_active);
+    const int64_t total = pp.g_tiles_per_frame * P.nf;
+    if (total == 0) return hipSuccess;
+    const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
+    if (pp.g_zpl == 2) hipLaunchKernelGGL((k_back_gather<2>), grid, block, 0, s, pp, sino, vol_out);
+    else hipLaunchKernelGGL((k_back_gather<1>), grid, block, 0, s, pp, sino, vol_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_back(const msf_plan &P, const float *sino, double *vol, bool with_active, hipStream_t s)
+{
+    if (P.tiles.back_mode == 1) return launch_back_gather(P, sino, vol, with_active, s);
+    return launch_back_scatter(P, sino, vol, with_active, s);
+}
+
+hipError_t launch_col_table(msf_plan &P, hipStream_t s)
+{
+    const ProjParams pp = P.proj_params(false);
+    const int64_t n = P.n_views * P.nu;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_col_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pp, P.n_views, P.d_cols);
     return hipGetLastError();
 }
