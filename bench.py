@@ -25,9 +25,6 @@ METRIC = "prox-map voxel·views/s at 1e-4 rel err: learned+batched vs plain CG; 
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0
 
-# residual tolerance per workload, frozen from the parity test against the
-# FP64 oracle (relative error of x <= 1e-4 at this recursive residual)
-FROZEN_TOL = {"c2": 1e-6, "c1": 1e-8, "c2s": 1e-6, "c3s": 1e-7}
 
 
 def parse():
@@ -86,6 +83,7 @@ def main():
     import torch
 
     from paper_2008_01567_amd import msf, synth
+    from paper_2008_01567_amd.calibration import FROZEN_TOL
 
     dev = torch.device("cuda:0")
     cfg = synth.config(args.config)
@@ -130,8 +128,9 @@ def main():
     tm = plan.get_timing()
     fwd_ms = tm["forward_ms"] / max(tm["forward_launches"], 1)
     back_ms = tm["back_ms"] / max(tm["back_launches"], 1)
-    dominant, dom_ms = ("forward projector k_forward", fwd_ms) if fwd_ms >= back_ms else \
-        ("backprojector k_back_scatter", back_ms)
+    back_name = "backprojector k_back_gather" if plan.get_tiles()["back_mode"] == 1 else \
+        "backprojector k_back_scatter"
+    dominant, dom_ms = ("forward projector k_forward", fwd_ms) if fwd_ms >= back_ms else (back_name, back_ms)
     nnz_total = int(nnz.sum())
     flops = 2.0 * nnz_total        # one FMA per ray-voxel intersection (SpMV convention)
     achieved = flops / (dom_ms * 1e-3) / 1e12
