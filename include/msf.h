@@ -92,6 +92,10 @@ typedef struct msf_tiles {
 
 enum { MSF_X0_V = 0, MSF_X0_USER = 1, MSF_X0_CNN = 2 };
 
+/* opts.cnn (MSF_X0_CNN): the solve computes g, predicts x0 with the network,
+ * and per frame keeps the prediction only if it is finite and its residual
+ * ||b - H x0|| is below that of v; otherwise the frame starts from v and the
+ * call returns MSF_CNN_FALLBACK (a warning). */
 typedef struct msf_solve_opts {
     double tol;                  /* stop frame n once ||b_n - H_n x_n|| <= tol ||b_n|| (recursive residual) */
     int32_t max_iter;            /* CG steps per frame (>= 0) */
@@ -155,6 +159,37 @@ msf_status msf_backproject(msf_plan *plan, const float *y, float *x, void *strea
  * MSF_EBREAKDOWN (x_out holds the last iterate) or an error. */
 msf_status msf_prox_solve(msf_plan *plan, const float *v, const float *y, const float *lambda, double sigma,
                           const msf_solve_opts *opts, float *x_out, msf_solve_stats *stats, void *stream);
+
+/* The learned start's residual feature g = (b - H v) / d_n for every frame
+ * (b - H v = A^T Lambda (y - A v), d_n = the frame's mean of
+ * diag(A^T Lambda A) + 1/sigma^2): the input the network sees besides v
+ * when msf_prox_solve runs with MSF_X0_CNN, exposed to build training data.
+ * g_out: device volume [n_frames][nz][ny][nx], overwritten.  Synchronises. */
+msf_status msf_prox_features(msf_plan *plan, const float *v, const float *y, const float *lambda, double sigma,
+                             float *g_out, void *stream);
+
+/* ---- learned warm start (not from the paper; plain CG stays the judge) ----
+ * Network: 3D CNN, 3x3x3 kernels, channels 2 -> 16 -> 16 -> 16 -> 1, ReLU
+ * after the first three layers, zero "same" padding:
+ *     x0 = v + c * f(v / c, g / c)
+ * with g the feature above and c the input scale.  Parameters are FP32
+ * (15169 values: per layer W[out][in][3][3][3] then b[out]); the kernels use
+ * BF16 weights and activations on the matrix cores with FP32 accumulation. */
+msf_status msf_cnn_create(const float *params_host, int64_t n_params, float in_scale, msf_cnn **out);
+void msf_cnn_destroy(msf_cnn *cnn);
+/* Current FP32 parameters (host [15169]). */
+msf_status msf_cnn_get_params(const msf_cnn *cnn, float *params_host);
+/* x0 = v + c f(v/c, g/c) for n volumes [n][nz][ny][nx] (device FP32). */
+msf_status msf_cnn_infer(msf_cnn *cnn, const float *v, const float *g, int32_t n, int32_t nz, int32_t ny,
+                         int32_t nx, float *x0, void *stream);
+/* One training step on the mean squared error between x0(v, g) and target
+ * (device FP32 volumes [n][nz][ny][nx]): forward, backward and, if apply,
+ * one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr.
+ * loss_out (host) receives the loss before the step; grad_out (host [15169],
+ * may be NULL) the FP32 gradient.  Synchronises the stream. */
+msf_status msf_cnn_train_step(msf_cnn *cnn, const float *v, const float *g, const float *target, int32_t n,
+                              int32_t nz, int32_t ny, int32_t nx, double lr, int32_t apply, double *loss_out,
+                              float *grad_out, void *stream);
 
 /* Live kernel timing.  While enabled, msf_prox_solve records HIP events on
  * the caller's stream around every forward-projector and backprojector launch

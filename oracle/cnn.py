@@ -4,18 +4,20 @@ The network is not from the paper: the paper's own denoisers are 2.5D CNNs
 (Sec. IV) whose weights are not available.  This is the small 3D network that
 predicts a starting point for the proximal-map solve:
 
-    input  c0 = v,  c1 = s * A^T y                       (2 channels)
-    h1 = relu(conv(c, W1) + b1)      2 -> 16
+    input  c0 = v / c,  c1 = g / c                        (2 channels)
+    h1 = relu(conv(input, W1) + b1)  2 -> 16
     h2 = relu(conv(h1, W2) + b2)    16 -> 16
     h3 = relu(conv(h2, W3) + b3)    16 -> 16
     f  = conv(h3, W4) + b4          16 -> 1
-    x0 = v + f
+    x0 = v + c * f
 
-``conv`` is 3x3x3 cross-correlation with zero "same" padding.  The GPU path
-stores weights and layer inputs in bfloat16 and accumulates in FP32; with
-``bf16=True`` this oracle rounds the same tensors to bfloat16 (round to
-nearest even) and does everything else in FP64, so the two differ only by
-accumulation order.
+where g is the data term's backprojected weighted residual at v (scaled to
+voxel units) and c a fixed input scale.  ``conv`` is 3x3x3 cross-correlation
+with zero "same" padding.  The GPU path stores weights, layer inputs and the
+gradients it feeds back into its matrix cores in bfloat16 and accumulates in
+FP32; with ``bf16=True`` this oracle rounds the same tensors at the same
+points (round to nearest even) and does everything else in FP64, so the two
+differ only by accumulation order.
 
 Every function is the definition written out tap by tap: forward, the input
 gradient (each output tap sends its gradient back to the input voxel it
@@ -81,10 +83,10 @@ def init_params(seed: int = 0, scale: float = 1.0):
     return params
 
 
-def forward(params, inp: np.ndarray, bf16: bool = False):
-    """inp [B, 2, Z, Y, X] (v, s*A^T y).  Returns (x0 [B,1,Z,Y,X], cache)."""
+def forward(params, inp: np.ndarray, bf16: bool = False, scale: float = 1.0):
+    """inp [B, 2, Z, Y, X] = (v, g) unscaled.  Returns (x0 [B,1,Z,Y,X], cache)."""
     rnd = bf16_round if bf16 else (lambda a: a)
-    h = rnd(inp)
+    h = rnd(inp / scale)
     cache = []
     for li, (w, b) in enumerate(params):
         wq = rnd(w)
@@ -94,21 +96,24 @@ def forward(params, inp: np.ndarray, bf16: bool = False):
             h = rnd(np.maximum(a, 0.0))
         else:
             h = a
-    return inp[:, 0:1] + h, cache
+    return inp[:, 0:1] + scale * h, {"layers": cache, "bf16": bf16, "scale": scale}
 
 
 def backward(params, cache, dx0: np.ndarray):
-    """Gradients of the loss w.r.t. every (W, b), given d loss / d x0."""
+    """Gradients of the loss w.r.t. every (W, b), given d loss / d x0.  With
+    bf16 the gradient entering each layer is rounded to bfloat16 (after the
+    ReLU mask), as the GPU feeds it to its matrix cores."""
+    layers, scale = cache["layers"], cache["scale"]
+    rnd = bf16_round if cache["bf16"] else (lambda a: a)
     grads = [None] * 4
-    g = dx0
+    g = rnd(dx0 * scale)
     for li in range(3, -1, -1):
-        h, wq, a = cache[li]
-        if li < 3:
-            g = g * (a > 0.0)
+        h, wq, a = layers[li]
         dw, db = conv3d_wgrad(h, g)
         grads[li] = (dw, db)
         if li > 0:
-            g = conv3d_dgrad(g, wq)
+            hp = layers[li - 1]
+            g = rnd(conv3d_dgrad(g, wq) * (hp[2] > 0.0))
     return grads
 
 

@@ -10,6 +10,7 @@
 #include <new>
 
 int64_t vol_chunk();
+hipError_t cnn_io_buffers(msf_cnn *C, int64_t n, float **g, float **x);
 
 namespace {
 thread_local std::string g_err;
@@ -373,6 +374,78 @@ msf_status msf_count_intersections(msf_plan *P, int64_t *per_frame, void *stream
     return MSF_OK;
 }
 
+namespace {
+
+// Transposes and checks the inputs, then computes ||b|| and r = b - H x for the
+// chosen start (v or a caller's x0).  Validation finishes before anything is
+// written to caller memory.
+msf_status prepare(msf_plan *P, const float *v, const float *y, const float *lam, double sigma, double tol,
+                   int max_iter, const float *x0_user, hipStream_t s)
+{
+    double *hc = (double *)P->host_stage;
+    int32_t *hflags = (int32_t *)(hc + 4);
+    hc[0] = 1.0 / (sigma * sigma);
+    hc[1] = tol;
+    hc[2] = (double)max_iter;
+    hc[3] = 0.0;
+    HIPCHK(hipMemcpyAsync(P->consts, hc, 4 * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(P->flags, 0, 4 * sizeof(int32_t), s));
+    HIPCHK(vol_to_internal(*P, v, P->vin, 1, P->flags + 2, s));
+    HIPCHK(sino_to_internal(*P, y, P->sy, 1, P->flags + 1, s));
+    HIPCHK(sino_to_internal(*P, lam, P->slam, 2, P->flags + 0, s));
+    if (x0_user) HIPCHK(vol_to_internal(*P, x0_user, P->x, 1, P->flags + 3, s));
+    else HIPCHK(launch_copy(P->x, P->vin, P->nvox_total, s));
+    HIPCHK(hipMemcpyAsync(hflags, P->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hflags[0] || hflags[1] || hflags[2] || hflags[3]) {
+        set_error("invalid input: " + std::to_string(hflags[0]) + " negative/non-finite lambda, " +
+                  std::to_string(hflags[1]) + " non-finite y, " + std::to_string(hflags[2]) + " non-finite v, " +
+                  std::to_string(hflags[3]) + " non-finite x0");
+        return MSF_EINVAL;
+    }
+    // ||b|| with b = A^T Lambda y + v / sigma^2
+    HIPCHK(launch_sino_mul(P->slam, P->sy, P->sz, P->nmeas_total, s));
+    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_vol_bnorm(*P, s));
+    HIPCHK(launch_scalar_reduce(*P, RW_BNORM, s));
+    // r = b - H x0, p = r
+    HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
+    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_vol_init_residual(*P, s));
+    HIPCHK(launch_scalar_reduce(*P, RW_INIT, s));
+    return MSF_OK;
+}
+
+// After prepare() from v: p = (b - H v) / d_f with d_f the frame's mean of
+// diag(A^T Lambda A) + 1/sigma^2 (estimated by A^T Lambda A applied to ones).
+msf_status feature(msf_plan *P, hipStream_t s)
+{
+    HIPCHK(launch_fill(P->p, P->nvox_total, 1.0f, s));
+    HIPCHK(launch_forward(*P, PM_WEIGHTED, P->p, nullptr, P->sz, false, s));
+    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
+    HIPCHK(launch_vol_sum_bp(*P, s));
+    HIPCHK(launch_scalar_reduce(*P, RW_DIAG, s));
+    HIPCHK(launch_scale_feature(*P, s));
+    return MSF_OK;
+}
+
+}  // namespace
+
+msf_status msf_prox_features(msf_plan *P, const float *v, const float *y, const float *lam, double sigma, float *g_out,
+                             void *stream)
+{
+    g_err.clear();
+    if (!P || !v || !y || !lam || !g_out) { set_error("null argument"); return MSF_EINVAL; }
+    if (!finite_pos(sigma)) { set_error("sigma must be positive and finite"); return MSF_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    msf_status st = prepare(P, v, y, lam, sigma, 0.0, 0, nullptr, s);
+    if (st != MSF_OK) return st;
+    if ((st = feature(P, s)) != MSF_OK) return st;
+    HIPCHK(vol_to_public(*P, P->p, g_out, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MSF_OK;
+}
+
 msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const float *lam, double sigma,
                           const msf_solve_opts *opts_in, float *x_out, msf_solve_stats *stats, void *stream)
 {
@@ -387,44 +460,33 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
         set_error("invalid solver options (tol >= 0, max_iter >= 0, check_every >= 1)"); return MSF_EINVAL;
     }
     if (o.x0_mode == MSF_X0_USER && !o.x0) { set_error("x0_mode USER needs x0"); return MSF_EINVAL; }
-    if (o.x0_mode == MSF_X0_CNN) { set_error("x0_mode CNN needs msf_prox_solve_learned"); return MSF_EINVAL; }
-    if (o.x0_mode != MSF_X0_V && o.x0_mode != MSF_X0_USER) { set_error("unknown x0_mode"); return MSF_EINVAL; }
+    if (o.x0_mode == MSF_X0_CNN && !o.cnn) { set_error("x0_mode CNN needs a network"); return MSF_EINVAL; }
+    if (o.x0_mode != MSF_X0_V && o.x0_mode != MSF_X0_USER && o.x0_mode != MSF_X0_CNN) {
+        set_error("unknown x0_mode"); return MSF_EINVAL;
+    }
     hipStream_t s = (hipStream_t)stream;
     const int nf = P->nf;
+    msf_status pst = prepare(P, v, y, lam, sigma, o.tol, o.max_iter, o.x0_mode == MSF_X0_USER ? o.x0 : nullptr, s);
+    if (pst != MSF_OK) return pst;
+    int32_t *hflags = (int32_t *)((double *)P->host_stage + 4);
 
-    // constants and input checks (validated before any output is written)
-    double *hc = (double *)P->host_stage;
-    int32_t *hflags = (int32_t *)(hc + 4);
-    hc[0] = 1.0 / (sigma * sigma);
-    hc[1] = o.tol;
-    hc[2] = (double)o.max_iter;
-    hc[3] = 0.0;
-    HIPCHK(hipMemcpyAsync(P->consts, hc, 4 * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(P->flags, 0, 4 * sizeof(int32_t), s));
-    HIPCHK(vol_to_internal(*P, v, P->vin, 1, P->flags + 2, s));
-    HIPCHK(sino_to_internal(*P, y, P->sy, 1, P->flags + 1, s));
-    HIPCHK(sino_to_internal(*P, lam, P->slam, 2, P->flags + 0, s));
-    if (o.x0_mode == MSF_X0_USER) HIPCHK(vol_to_internal(*P, o.x0, P->x, 1, P->flags + 3, s));
-    else HIPCHK(launch_copy(P->x, P->vin, P->nvox_total, s));
-    HIPCHK(hipMemcpyAsync(hflags, P->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hflags[0] || hflags[1] || hflags[2] || hflags[3]) {
-        set_error("invalid input: " + std::to_string(hflags[0]) + " negative/non-finite lambda, " +
-                  std::to_string(hflags[1]) + " non-finite y, " + std::to_string(hflags[2]) + " non-finite v, " +
-                  std::to_string(hflags[3]) + " non-finite x0");
-        return MSF_EINVAL;
+    if (o.x0_mode == MSF_X0_CNN) {
+        // learned start x_cnn = v + c f(v / c, g / c); kept per frame only if
+        // finite and with a smaller residual than v (else the frame starts at v)
+        msf_cnn *C = const_cast<msf_cnn *>(o.cnn);
+        msf_status fs = feature(P, s);
+        if (fs != MSF_OK) return fs;
+        float *gpub = nullptr, *xpub = nullptr;
+        HIPCHK(cnn_io_buffers(C, P->nvox_total, &gpub, &xpub));
+        HIPCHK(vol_to_public(*P, P->p, gpub, s));
+        HIPCHK(cnn_infer_internal(C, v, gpub, P->nf, P->nz, P->ny, P->nx, xpub, s));
+        HIPCHK(vol_to_internal(*P, xpub, P->x, 0, nullptr, s));
+        HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
+        HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
+        HIPCHK(launch_vol_residual_p(*P, s));
+        HIPCHK(launch_scalar_reduce(*P, RW_CNN, s));
+        HIPCHK(launch_vol_select(*P, s));
     }
-
-    // ||b|| with b = A^T Lambda y + v / sigma^2
-    HIPCHK(launch_sino_mul(P->slam, P->sy, P->sz, P->nmeas_total, s));
-    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
-    HIPCHK(launch_vol_bnorm(*P, s));
-    HIPCHK(launch_scalar_reduce(*P, RW_BNORM, s));
-    // r = b - H x0, p = r
-    HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
-    HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
-    HIPCHK(launch_vol_init_residual(*P, s));
-    HIPCHK(launch_scalar_reduce(*P, RW_INIT, s));
 
     // CG steps: one captured graph holds a whole check period (check_every
     // steps of six launches each); a shorter last period runs eagerly.
@@ -515,7 +577,7 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
             if (stats->rel_residual) stats->rel_residual[f] = rel;
             if (stats->true_rel_residual) stats->true_rel_residual[f] = o.true_residual ? hs[SC_TRUE * nf + f] : -1.0;
             if (stats->converged) stats->converged[f] = conv ? 1 : 0;
-            if (stats->cnn_used) stats->cnn_used[f] = 0;
+            if (stats->cnn_used) stats->cnn_used[f] = o.x0_mode == MSF_X0_CNN ? (uint8_t)hi[IS_CNN * nf + f] : 0;
         }
     }
     if (P->timing && !step_fwd_ms.empty()) {
@@ -529,6 +591,9 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
             P->n_back++;
         }
     }
+    if (st == MSF_OK && o.x0_mode == MSF_X0_CNN)
+        for (int f = 0; f < nf; ++f)
+            if (!hi[IS_CNN * nf + f]) st = MSF_CNN_FALLBACK;
     if (st == MSF_EBREAKDOWN) set_error("CG breakdown: <p, H p> <= 0 or non-finite on some frame");
     if (stats) {
         stats->steps = steps;

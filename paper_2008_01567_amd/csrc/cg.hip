@@ -136,8 +136,8 @@ __global__ __launch_bounds__(VB) void k_vol_bnorm(VolArgs A)
     if (threadIdx.x == 0) A.part[(int64_t)f * A.bpf + blockIdx.x] = s;
 }
 
-// r = A^T Lambda (y - A x) (in bp) + (v - x) / sigma^2 = b - H x;  p = r;  clears bp.
-// With store == 0 only ||r||^2 partials (the true residual of the final x).
+// r = A^T Lambda (y - A x) (in bp) + (v - x) / sigma^2 = b - H x;  clears bp.
+// store 1: r = p = that residual; store 2: p only; store 0: only ||.||^2 partials.
 __global__ __launch_bounds__(VB) void k_vol_residual(VolArgs A, int store)
 {
     const int f = blockIdx.y;
@@ -149,16 +149,62 @@ __global__ __launch_bounds__(VB) void k_vol_residual(VolArgs A, int store)
         if (i < A.nvox) {
             const double rv = A.bp[base + i] + ((double)A.vin[base + i] - (double)A.x[base + i]) * is2;
             const float rf = (float)rv;
-            if (store) {
-                A.r[base + i] = rf;
-                A.p[base + i] = rf;
-            }
+            if (store == 1) A.r[base + i] = rf;
+            if (store) A.p[base + i] = rf;
             s += store ? (double)rf * (double)rf : rv * rv;
             A.bp[base + i] = 0.0;
         }
     }
     s = block_sum(s);
     if (threadIdx.x == 0) A.part[(int64_t)f * A.bpf + blockIdx.x] = s;
+}
+
+// sum of bp per frame (partials), clears bp
+__global__ __launch_bounds__(VB) void k_vol_sum_bp(VolArgs A)
+{
+    const int f = blockIdx.y;
+    const int64_t base = (int64_t)f * A.nvox;
+    double s = 0.0;
+    for (int k = 0; k < VE; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
+        if (i < A.nvox) {
+            s += A.bp[base + i];
+            A.bp[base + i] = 0.0;
+        }
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) A.part[(int64_t)f * A.bpf + blockIdx.x] = s;
+}
+
+// p = r / diag_f
+__global__ __launch_bounds__(VB) void k_scale_feature(VolArgs A)
+{
+    const int f = blockIdx.y;
+    const double inv = 1.0 / A.scal[SC_DIAG * A.nf + f];
+    const int64_t base = (int64_t)f * A.nvox;
+    for (int k = 0; k < VE; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
+        if (i < A.nvox) A.p[base + i] = (float)((double)A.r[base + i] * inv);
+    }
+}
+
+// per frame: learned start kept (IS_CNN = 1): r = p; else x = v, p = r
+__global__ __launch_bounds__(VB) void k_vol_select(VolArgs A, const int32_t *use_cnn)
+{
+    const int f = blockIdx.y;
+    const bool keep = use_cnn[f] != 0;
+    const int64_t base = (int64_t)f * A.nvox;
+    for (int k = 0; k < VE; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
+        if (i < A.nvox) {
+            if (keep) {
+                A.r[base + i] = A.p[base + i];
+            } else {
+                A.x[base + i] = A.vin[base + i];
+                A.p[base + i] = A.r[base + i];
+            }
+        }
+    }
 }
 
 // x += alpha p;  r -= alpha (bp + p / sigma^2);  bp = 0;  partial ||r||^2.
@@ -208,6 +254,7 @@ __global__ __launch_bounds__(VB) void k_update_p(VolArgs A)
 
 // ------------------------------------------------------- frame scalars --
 struct ScalArgs {
+    int64_t nvox;
     const double *part_vol;     // [nf * bpf]
     const double *part_proj;    // [total tiles]
     const int64_t *tile_offset; // [nf + 1]
@@ -244,9 +291,26 @@ __global__ __launch_bounds__(VB) void k_red_setup(ScalArgs A, int what)
         I(A, IS_STATUS, f) = 0;
         const bool done = (bn > 0.0 ? rel <= A.consts[1] : s == 0.0) || A.consts[2] < 1.0;
         I(A, IS_ACTIVE, f) = done ? 0 : 1;
-    } else {
+    } else if (what == RW_TRUE) {
         const double bn = S(A, SC_BNORM, f);
         S(A, SC_TRUE, f) = bn > 0.0 ? sqrt(s) / bn : sqrt(s);
+    } else if (what == RW_DIAG) {
+        // mean of A^T Lambda A 1 over the frame's voxels, plus the 1/sigma^2 of H
+        S(A, SC_DIAG, f) = s / (double)A.nvox + A.consts[0];
+    } else {
+        // learned start: keep it where it is finite and beats the residual of v
+        S(A, SC_GCNN, f) = s;
+        const bool keep = isfinite(s) && s < S(A, SC_GAMMA, f);
+        I(A, IS_CNN, f) = keep ? 1 : 0;
+        if (keep) {
+            const double bn = S(A, SC_BNORM, f);
+            const double rel = bn > 0.0 ? sqrt(s) / bn : sqrt(s);
+            S(A, SC_GAMMA, f) = s;
+            S(A, SC_PP, f) = s;
+            S(A, SC_REL, f) = rel;
+            const bool done = (bn > 0.0 ? rel <= A.consts[1] : s == 0.0) || A.consts[2] < 1.0;
+            I(A, IS_ACTIVE, f) = done ? 0 : 1;
+        }
     }
 }
 
@@ -307,6 +371,7 @@ VolArgs vol_args(msf_plan &P, bool with_active)
 ScalArgs scal_args(msf_plan &P)
 {
     ScalArgs A;
+    A.nvox = P.nvox;
     A.part_vol = P.part_vol;
     A.part_proj = P.part_proj;
     A.tile_offset = P.d_tile_offset;
@@ -381,6 +446,30 @@ hipError_t launch_vol_init_residual(msf_plan &P, hipStream_t s)
 hipError_t launch_vol_true_residual(msf_plan &P, hipStream_t s)
 {
     hipLaunchKernelGGL(k_vol_residual, vol_grid(P), dim3(VB), 0, s, vol_args(P, false), 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_vol_sum_bp(msf_plan &P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vol_sum_bp, vol_grid(P), dim3(VB), 0, s, vol_args(P, false));
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_feature(msf_plan &P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_feature, vol_grid(P), dim3(VB), 0, s, vol_args(P, false));
+    return hipGetLastError();
+}
+
+hipError_t launch_vol_residual_p(msf_plan &P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vol_residual, vol_grid(P), dim3(VB), 0, s, vol_args(P, false), 2);
+    return hipGetLastError();
+}
+
+hipError_t launch_vol_select(msf_plan &P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vol_select, vol_grid(P), dim3(VB), 0, s, vol_args(P, false), P.iscal + IS_CNN * P.nf);
     return hipGetLastError();
 }
 

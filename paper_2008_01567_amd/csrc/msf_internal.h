@@ -68,9 +68,11 @@ enum ScalarSlot : int {
     SC_BNORM,       // ||b||
     SC_REL,         // ||r|| / ||b||
     SC_TRUE,        // true relative residual
+    SC_DIAG,        // mean over voxels of diag(A^T Lambda A) (row-sum estimate) + 1/sigma^2
+    SC_GCNN,        // ||b - H x_cnn||^2
     SC_COUNT
 };
-enum IScalarSlot : int { IS_ACTIVE = 0, IS_ITERS, IS_STATUS, IS_COUNT };
+enum IScalarSlot : int { IS_ACTIVE = 0, IS_ITERS, IS_STATUS, IS_CNN, IS_COUNT };
 // global solve constants live in consts[]: [0] = 1/sigma^2, [1] = tol, [2] = max_iter
 
 struct msf_plan {
@@ -161,4 +163,16 @@ enum ReduceWhat : int {
     RW_BNORM = 0,      // part_vol -> SC_BNORM
     RW_INIT = 1,       // part_vol -> SC_GAMMA, SC_PP = SC_GAMMA, active flags
     RW_TRUE = 2,       // part_vol -> SC_TRUE
+    RW_DIAG = 3,       // part_vol (sum of A^T Lambda A 1) -> SC_DIAG
+    RW_CNN = 4,        // part_vol -> SC_GCNN, then choose the start per frame (IS_CNN)
 };
+hipError_t launch_vol_sum_bp(msf_plan &P, hipStream_t s);
+// p = r / diag_f (the network's residual feature, internal layout)
+hipError_t launch_scale_feature(msf_plan &P, hipStream_t s);
+// r = b - H x into p only (the learned start's residual), partial ||.||^2
+hipError_t launch_vol_residual_p(msf_plan &P, hipStream_t s);
+// per frame: keep the learned start (r = p) or go back to v (x = v, p = r)
+hipError_t launch_vol_select(msf_plan &P, hipStream_t s);
+// network evaluation (cnn.hip): x0 = v + c f(v / c, g / c) on public-layout volumes
+hipError_t cnn_infer_internal(struct msf_cnn *C, const float *v, const float *g, int N, int Z, int Y, int X, float *x0,
+                              hipStream_t s);

@@ -67,7 +67,8 @@ _lib = None
 EXPORTS = ["msf_solve_opts_default", "msf_plan_create", "msf_plan_destroy", "msf_plan_set_tiles",
            "msf_plan_get_tiles", "msf_plan_sizes", "msf_project", "msf_backproject", "msf_prox_solve",
            "msf_last_error", "msf_version", "msf_plan_set_timing", "msf_plan_get_timing",
-           "msf_count_intersections"]
+           "msf_count_intersections", "msf_prox_features", "msf_cnn_create", "msf_cnn_destroy",
+           "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step"]
 
 
 def lib():
@@ -93,8 +94,16 @@ def lib():
         L.msf_plan_set_timing.argtypes = [vp, C.c_int32]
         L.msf_plan_get_timing.argtypes = [vp, C.POINTER(msf_timing)]
         L.msf_count_intersections.argtypes = [vp, C.POINTER(C.c_int64), vp]
+        L.msf_prox_features.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
+        L.msf_cnn_create.argtypes = [C.POINTER(C.c_float), C.c_int64, C.c_float, C.POINTER(vp)]
+        L.msf_cnn_destroy.argtypes = [vp]
+        L.msf_cnn_get_params.argtypes = [vp, C.POINTER(C.c_float)]
+        L.msf_cnn_infer.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp]
+        L.msf_cnn_train_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                         C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_float), vp]
         for name in EXPORTS:
-            if name not in ("msf_last_error", "msf_version", "msf_plan_destroy", "msf_solve_opts_default"):
+            if name not in ("msf_last_error", "msf_version", "msf_plan_destroy", "msf_solve_opts_default",
+                            "msf_cnn_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -197,8 +206,17 @@ class Plan:
         _check(lib().msf_backproject(self._h, _ptr(y, self.n_meas), _ptr(x, self.n_vox), _stream(stream)))
         return x
 
+    def features(self, v, y, lam, sigma, out=None, stream=None):
+        """The learned start's residual feature g (msf_prox_features)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=torch.float32, device=v.device)
+        _check(lib().msf_prox_features(self._h, _ptr(v, self.n_vox), _ptr(y, self.n_meas), _ptr(lam, self.n_meas),
+                                       float(sigma), _ptr(out, self.n_vox), _stream(stream)))
+        return out
+
     def prox_solve(self, v, y, lam, sigma, tol=1e-6, max_iter=1000, check_every=8, x0=None, use_graph=True,
-                   true_residual=False, out=None, stream=None):
+                   true_residual=False, out=None, stream=None, cnn=None):
         """Returns (x, stats) with stats a dict of per-frame arrays and the status code."""
         import torch
         nf = self.geom.n_frames
@@ -211,6 +229,9 @@ class Plan:
         if x0 is not None:
             o.x0_mode = MSF_X0_USER
             o.x0 = _ptr(x0, self.n_vox).value
+        if cnn is not None:
+            o.x0_mode = MSF_X0_CNN
+            o.cnn = cnn._h.value
         iters = np.zeros(nf, dtype=np.int32)
         rel = np.zeros(nf)
         trel = np.zeros(nf)
@@ -225,3 +246,52 @@ class Plan:
         return out, {"status": status, "iters": iters, "rel_residual": rel, "true_rel_residual": trel,
                      "converged": conv.astype(bool), "cnn_used": used.astype(bool), "steps": st.steps,
                      "seconds": st.seconds}
+
+
+N_CNN_PARAMS = 15169
+
+
+class Cnn:
+    """The warm-start network (msf_cnn_*).  params: FP32 [15169] (per layer
+    W[out][in][3][3][3] then b[out]); in_scale: the input scale c."""
+
+    def __init__(self, params, in_scale):
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        h = C.c_void_p()
+        _check(lib().msf_cnn_create(p.ctypes.data_as(C.POINTER(C.c_float)), p.size, float(in_scale), C.byref(h)))
+        self._h = h
+        self.in_scale = float(in_scale)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().msf_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(N_CNN_PARAMS, dtype=np.float32)
+        _check(lib().msf_cnn_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def infer(self, v, g, out=None, stream=None):
+        import torch
+        n, nz, ny, nx = v.shape
+        if out is None:
+            out = torch.empty_like(v)
+        _check(lib().msf_cnn_infer(self._h, _ptr(v), _ptr(g, v.numel()), n, nz, ny, nx, _ptr(out, v.numel()),
+                                   _stream(stream)))
+        return out
+
+    def train_step(self, v, g, target, lr=1e-3, apply=True, want_grad=False, stream=None):
+        n, nz, ny, nx = v.shape
+        loss = C.c_double()
+        grad = np.zeros(N_CNN_PARAMS, dtype=np.float32) if want_grad else None
+        gp = grad.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
+        _check(lib().msf_cnn_train_step(self._h, _ptr(v), _ptr(g, v.numel()), _ptr(target, v.numel()), n, nz, ny, nx,
+                                        float(lr), int(bool(apply)), C.byref(loss), gp, _stream(stream)))
+        return loss.value, grad

@@ -67,6 +67,34 @@ def test_network_gradients_match_autograd():
         assert np.allclose(gb, b.grad.numpy(), rtol=1e-10, atol=1e-12)
 
 
+def test_scaled_network_matches_unscaled_definition():
+    """x0 = v + c f(v/c, g/c): the scale only rescales the inputs and the output."""
+    rng = np.random.default_rng(8)
+    params = _rand_params(9)
+    inp = rng.standard_normal((1, 2, 4, 5, 6))
+    c = 0.05
+    a, _ = cnn.forward(params, inp, scale=c)
+    b, _ = cnn.forward(params, inp / c)
+    assert np.allclose(a, inp[:, 0:1] + c * (b - inp[:, 0:1] / c), rtol=1e-12, atol=1e-14)
+
+
+def test_bf16_backward_rounds_at_the_documented_points():
+    rng = np.random.default_rng(10)
+    params = _rand_params(11)
+    inp = rng.standard_normal((1, 2, 4, 4, 4))
+    target = rng.standard_normal((1, 1, 4, 4, 4))
+    out, cache = cnn.forward(params, inp, bf16=True, scale=0.5)
+    grads = cnn.backward(params, cache, cnn.mse(out, target)[1])
+    out64, cache64 = cnn.forward(params, inp, scale=0.5)
+    grads64 = cnn.backward(params, cache64, cnn.mse(out64, target)[1])
+    # bf16 storage changes the result at the bf16 level, not more
+    for (gw, gb), (hw, hb) in zip(grads, grads64):
+        assert np.linalg.norm(gw - hw) <= 0.05 * np.linalg.norm(hw)
+    # the layer inputs of the bf16 path are bf16 numbers
+    for h, wq, a in cache["layers"]:
+        assert np.array_equal(h, cnn.bf16_round(h)) and np.array_equal(wq, cnn.bf16_round(wq))
+
+
 def test_network_gradients_central_differences():
     rng = np.random.default_rng(4)
     params = _rand_params(5)
