@@ -4,8 +4,11 @@
 One step = one call of the whole hot path on one batch: the proximal map of
 the data term (paper eq. (mace_L)) for all 16 frames of the 128^3 x 16
 workload (192^2 detector, 16 interlaced views per frame over 360 degrees),
-solved by the HIP library's batched CG to the frozen stopping rule.  Inputs
-are resident in HBM before the timed region starts.
+solved by the HIP library's batched CG to the frozen stopping rule, started
+from the trained network's prediction (learned + batched; the network's
+evaluation and the residual checks of its start are inside the step).  The
+same step started from v (plain batched CG) is timed beside it.  Inputs are
+resident in HBM before the timed region starts.
 
 Prints ONE JSON line.  Metric: voxel.views per second of solved proximal maps
 (sum over frames of voxels x views, divided by the wall time of the solve).
@@ -37,6 +40,7 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=6000)
     ap.add_argument("--check-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="time plain batched CG only")
     ap.add_argument("--cpu-iters", type=int, default=40, help="FP64 CG iterations timed in the CPU sample")
     ap.add_argument("--tiles", default="", help="rays_per_lane,waves_per_group,xcd_remap (default: plan default)")
     return ap.parse_args()
@@ -107,25 +111,43 @@ def main():
     nnz = plan.count_intersections()
     log("setup %.1fs, nnz per frame %s" % (time.perf_counter() - t0, nnz[:4].tolist()))
 
-    def solve():
-        return plan.prox_solve(v, y, lam, cfg.sigma, tol=tol, max_iter=args.max_iter,
-                               check_every=args.check_every, use_graph=True, out=out)
+    net = None
+    if not args.no_learned:
+        try:
+            from paper_2008_01567_amd import train_cnn
+            params, scales, meta = train_cnn.load(args.config)
+            net = msf.Cnn(params, scales)
+            log("warm-start network: trained on %d frames of %s" % (meta["frames"], meta["config"]))
+        except FileNotFoundError:
+            log("no trained warm-start network for %s: learned leg skipped" % args.config)
 
-    for i in range(args.warmup):
-        _, st = solve()
-        log("warmup %d: iters %s steps %d %.3fs" % (i, st["iters"].tolist(), st["steps"], st["seconds"]))
-    plan.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(args.steps):
-        _, st = solve()
-        stats.append(st)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / max(args.steps, 1)
-    st = stats[-1]
-    log("step: %.3fs, iters %s, status %d" % (dt, st["iters"].tolist(), st["status"]))
-    tm = plan.get_timing()
+    def solve(cnn=None):
+        return plan.prox_solve(v, y, lam, cfg.sigma, tol=tol, max_iter=args.max_iter,
+                               check_every=args.check_every, use_graph=True, out=out, cnn=cnn)
+
+    def timed(cnn):
+        for i in range(args.warmup):
+            _, st = solve(cnn)
+            log("warmup %d (%s): iters %s steps %d %.3fs" % (i, "learned" if cnn else "plain", st["iters"].tolist(),
+                                                            st["steps"], st["seconds"]))
+        plan.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for i in range(args.steps):
+            _, st = solve(cnn)
+            stats.append(st)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(args.steps, 1)
+        log("step (%s): %.3fs, iters %s, status %d" % ("learned" if cnn else "plain", dt, stats[-1]["iters"].tolist(),
+                                                       stats[-1]["status"]))
+        return dt, stats[-1], plan.get_timing()
+
+    dt_plain, st_plain, tm_plain = timed(None)
+    if net is not None:
+        dt, st, tm = timed(net)
+    else:
+        dt, st, tm = dt_plain, st_plain, tm_plain
     fwd_ms = tm["forward_ms"] / max(tm["forward_launches"], 1)
     back_ms = tm["back_ms"] / max(tm["back_launches"], 1)
     back_name = "backprojector k_back_gather" if plan.get_tiles()["back_mode"] == 1 else \
@@ -144,17 +166,26 @@ def main():
                                "sigma %.2g, stop at rel. residual %.0e" %
                                (args.config, geom.nx, geom.ny, geom.nz, geom.n_frames, geom.nu, geom.nv,
                                 geom.views_of(0), cfg.schedule, cfg.sigma, tol),
-                   "solver": "plain batched CG (FP32 vectors, FP64 scalars), hipGraph per %d steps" %
-                             args.check_every,
+                   "solver": "%s batched CG (FP32 vectors, FP64 scalars), hipGraph per %d steps" %
+                             ("learned-warm-start +" if net is not None else "plain", args.check_every),
                    "tiles": plan.get_tiles()},
         "cg_iters": {"mean": float(np.mean(st["iters"])), "max": int(np.max(st["iters"]))},
+        "plain_batched": {"value": voxel_views / dt_plain, "ms_per_step": dt_plain * 1e3,
+                          "cg_iters_mean": float(np.mean(st_plain["iters"])),
+                          "start_rel_residual": float(np.mean(st_plain["start_rel_residual"]))},
+        "learned_batched": None if net is None else {
+            "value": voxel_views / dt, "ms_per_step": dt * 1e3, "cg_iters_mean": float(np.mean(st["iters"])),
+            "frames_kept": int(np.sum(st["cnn_used"])),
+            "start_rel_residual": float(np.mean(st["start_rel_residual"]))},
+        "speedup_learned_vs_plain": None if net is None else dt_plain / dt,
         "kernels_ms": {"forward": fwd_ms, "back": back_ms, "timed_launches": tm["forward_launches"]},
         "nnz_A": nnz_total,
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(cfg, geom, v_np, y_np, lam_np, int(st["iters"][0]), args.cpu_iters)
+        result["cpu_baseline"] = cpu_baseline(cfg, geom, v_np, y_np, lam_np, int(st_plain["iters"][0]),
+                                              args.cpu_iters)
     print(json.dumps(result), flush=True)
 
 

@@ -114,6 +114,7 @@ typedef struct msf_solve_stats {
     double *true_rel_residual;   /* host [n_frames] or NULL: recomputed (true_residual = 1), else -1 */
     uint8_t *converged;          /* host [n_frames] or NULL */
     uint8_t *cnn_used;           /* host [n_frames] or NULL: 1 if the learned start was kept */
+    double *start_rel_residual;  /* host [n_frames] or NULL: ||b - H x0|| / ||b|| of the start used */
     int32_t steps;               /* out: CG steps launched for the batch */
     int32_t reserved;
     double seconds;              /* out: wall time of the call (host clock) */
@@ -171,15 +172,16 @@ msf_status msf_prox_features(msf_plan *plan, const float *v, const float *y, con
 /* ---- learned warm start (not from the paper; plain CG stays the judge) ----
  * Network: 3D CNN, 3x3x3 kernels, channels 2 -> 16 -> 16 -> 16 -> 1, ReLU
  * after the first three layers, zero "same" padding:
- *     x0 = v + c * f(v / c, g / c)
- * with g the feature above and c the input scale.  Parameters are FP32
+ *     x0 = v + c_o * f(v / c_v, g / c_g)
+ * with g the feature above and scales (c_v, c_g, c_o).  Parameters are FP32
  * (15169 values: per layer W[out][in][3][3][3] then b[out]); the kernels use
  * BF16 weights and activations on the matrix cores with FP32 accumulation. */
-msf_status msf_cnn_create(const float *params_host, int64_t n_params, float in_scale, msf_cnn **out);
+msf_status msf_cnn_create(const float *params_host, int64_t n_params, const float *scales_host /* [3] */,
+                          msf_cnn **out);
 void msf_cnn_destroy(msf_cnn *cnn);
 /* Current FP32 parameters (host [15169]). */
 msf_status msf_cnn_get_params(const msf_cnn *cnn, float *params_host);
-/* x0 = v + c f(v/c, g/c) for n volumes [n][nz][ny][nx] (device FP32). */
+/* x0 = v + c_o f(v/c_v, g/c_g) for n volumes [n][nz][ny][nx] (device FP32). */
 msf_status msf_cnn_infer(msf_cnn *cnn, const float *v, const float *g, int32_t n, int32_t nz, int32_t ny,
                          int32_t nx, float *x0, void *stream);
 /* One training step on the mean squared error between x0(v, g) and target

@@ -4,15 +4,15 @@ The network is not from the paper: the paper's own denoisers are 2.5D CNNs
 (Sec. IV) whose weights are not available.  This is the small 3D network that
 predicts a starting point for the proximal-map solve:
 
-    input  c0 = v / c,  c1 = g / c                        (2 channels)
+    input  c0 = v / c_v,  c1 = g / c_g                    (2 channels)
     h1 = relu(conv(input, W1) + b1)  2 -> 16
     h2 = relu(conv(h1, W2) + b2)    16 -> 16
     h3 = relu(conv(h2, W3) + b3)    16 -> 16
     f  = conv(h3, W4) + b4          16 -> 1
-    x0 = v + c * f
+    x0 = v + c_o * f
 
 where g is the data term's backprojected weighted residual at v (scaled to
-voxel units) and c a fixed input scale.  ``conv`` is 3x3x3 cross-correlation
+voxel units) and c_v, c_g, c_o fixed scales stored with the network.  ``conv`` is 3x3x3 cross-correlation
 with zero "same" padding.  The GPU path stores weights, layer inputs and the
 gradients it feeds back into its matrix cores in bfloat16 and accumulates in
 FP32; with ``bf16=True`` this oracle rounds the same tensors at the same
@@ -83,10 +83,12 @@ def init_params(seed: int = 0, scale: float = 1.0):
     return params
 
 
-def forward(params, inp: np.ndarray, bf16: bool = False, scale: float = 1.0):
-    """inp [B, 2, Z, Y, X] = (v, g) unscaled.  Returns (x0 [B,1,Z,Y,X], cache)."""
+def forward(params, inp: np.ndarray, bf16: bool = False, scale=1.0):
+    """inp [B, 2, Z, Y, X] = (v, g) unscaled; scale = c or (c_v, c_g, c_o).
+    Returns (x0 [B,1,Z,Y,X], cache)."""
     rnd = bf16_round if bf16 else (lambda a: a)
-    h = rnd(inp / scale)
+    cv, cg, co = (scale, scale, scale) if np.isscalar(scale) else scale
+    h = rnd(np.concatenate([inp[:, 0:1] / cv, inp[:, 1:2] / cg], axis=1))
     cache = []
     for li, (w, b) in enumerate(params):
         wq = rnd(w)
@@ -96,7 +98,7 @@ def forward(params, inp: np.ndarray, bf16: bool = False, scale: float = 1.0):
             h = rnd(np.maximum(a, 0.0))
         else:
             h = a
-    return inp[:, 0:1] + scale * h, {"layers": cache, "bf16": bf16, "scale": scale}
+    return inp[:, 0:1] + co * h, {"layers": cache, "bf16": bf16, "scale": co}
 
 
 def backward(params, cache, dx0: np.ndarray):

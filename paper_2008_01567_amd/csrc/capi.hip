@@ -416,6 +416,15 @@ msf_status prepare(msf_plan *P, const float *v, const float *y, const float *lam
     return MSF_OK;
 }
 
+// host copy of the per-frame relative residual of the start (SC_REL right after setup)
+msf_status start_residual(msf_plan *P, std::vector<double> &out, hipStream_t s)
+{
+    out.assign(P->nf, 0.0);
+    HIPCHK(hipMemcpyAsync(out.data(), P->scal + SC_REL * P->nf, sizeof(double) * P->nf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MSF_OK;
+}
+
 // After prepare() from v: p = (b - H v) / d_f with d_f the frame's mean of
 // diag(A^T Lambda A) + 1/sigma^2 (estimated by A^T Lambda A applied to ones).
 msf_status feature(msf_plan *P, hipStream_t s)
@@ -486,6 +495,11 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
         HIPCHK(launch_vol_residual_p(*P, s));
         HIPCHK(launch_scalar_reduce(*P, RW_CNN, s));
         HIPCHK(launch_vol_select(*P, s));
+    }
+    std::vector<double> rel0;
+    if (stats && stats->start_rel_residual) {
+        msf_status rs = start_residual(P, rel0, s);
+        if (rs != MSF_OK) return rs;
     }
 
     // CG steps: one captured graph holds a whole check period (check_every
@@ -578,6 +592,7 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
             if (stats->true_rel_residual) stats->true_rel_residual[f] = o.true_residual ? hs[SC_TRUE * nf + f] : -1.0;
             if (stats->converged) stats->converged[f] = conv ? 1 : 0;
             if (stats->cnn_used) stats->cnn_used[f] = o.x0_mode == MSF_X0_CNN ? (uint8_t)hi[IS_CNN * nf + f] : 0;
+            if (stats->start_rel_residual) stats->start_rel_residual[f] = rel0[f];
         }
     }
     if (P->timing && !step_fwd_ms.empty()) {

@@ -1,8 +1,8 @@
 // Learned warm start of the proximal-map solve: a 4-layer 3D CNN
 // (3x3x3 kernels, channels 2 -> 16 -> 16 -> 16 -> 1, ReLU after the first
-// three layers) predicting x0 = v + c f(v / c, g / c), where g is the data
-// term's backprojected weighted residual at v in voxel units and c a fixed
-// input scale.  The paper has no such network (its denoisers are 2.5D CNNs of
+// three layers) predicting x0 = v + c_o f(v / c_v, g / c_g), where g is the
+// data term's backprojected weighted residual at v in voxel units and c_v,
+// c_g, c_o are fixed scales stored with the network.  The paper has no such network (its denoisers are 2.5D CNNs of
 // a different kind); plain CG remains the fallback and the judge of the
 // prediction.
 //
@@ -218,14 +218,14 @@ __global__ void k_pack(const float *__restrict__ master, uint16_t *__restrict__ 
     if (k < CH) bias[layer * CH + k] = k < cout ? master[POFF[layer] + cout * cin * TAPS + k] : 0.0f;
 }
 
-// input channels: bf16(v / c), bf16(g / c), zeros
-__global__ void k_pack_input(const float *__restrict__ v, const float *__restrict__ gin, int64_t n, float inv_c,
-                             uint16_t *__restrict__ h0)
+// input channels: bf16(v / c_v), bf16(g / c_g), zeros
+__global__ void k_pack_input(const float *__restrict__ v, const float *__restrict__ gin, int64_t n, float inv_cv,
+                             float inv_cg, uint16_t *__restrict__ h0)
 {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * CH; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t vox = e / CH;
         const int c = (int)(e % CH);
-        h0[e] = c == 0 ? f2bf(v[vox] * inv_c) : (c == 1 ? f2bf(gin[vox] * inv_c) : (uint16_t)0);
+        h0[e] = c == 0 ? f2bf(v[vox] * inv_cv) : (c == 1 ? f2bf(gin[vox] * inv_cg) : (uint16_t)0);
     }
 }
 
@@ -280,7 +280,7 @@ unsigned grid_of(int64_t work, int per_block)
 }  // namespace
 
 struct msf_cnn {
-    float c = 1.0f;
+    float cv = 1.0f, cg = 1.0f, co = 1.0f;   // input / feature / output scales
     float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     uint16_t *wf = nullptr, *wd = nullptr;
     float *bias = nullptr;
@@ -352,14 +352,15 @@ hipError_t cnn_forward(msf_cnn *C, const float *v, const float *gin, int N, int 
 {
     const int64_t n = (int64_t)N * Z * Y * X;
     hipError_t e;
-    hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n * CH, 256)), dim3(256), 0, s, v, gin, n, 1.0f / C->c, C->h[0]);
+    hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n * CH, 256)), dim3(256), 0, s, v, gin, n, 1.0f / C->cv,
+                       1.0f / C->cg, C->h[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int l = 0; l < 3; ++l)
         if ((e = launch_conv(EPI_RELU, C->h[l], C->wf + l * WPACK, C->bias + l * CH, N, Z, Y, X, C->h[l + 1],
                              nullptr, nullptr, nullptr, 0.0f, s)) != hipSuccess)
             return e;
     return launch_conv(EPI_RESID, C->h[3], C->wf + 3 * WPACK, C->bias + 3 * CH, N, Z, Y, X, nullptr, nullptr, x0, v,
-                       C->c, s);
+                       C->co, s);
 }
 
 hipError_t cnn_pack(msf_cnn *C, hipStream_t s)
@@ -401,18 +402,25 @@ hipError_t cnn_infer_internal(msf_cnn *C, const float *v, const float *g, int N,
 
 extern "C" {
 
-msf_status msf_cnn_create(const float *params, int64_t n_params, float in_scale, msf_cnn **out)
+msf_status msf_cnn_create(const float *params, int64_t n_params, const float *scales, msf_cnn **out)
 {
     set_error("");
-    if (!params || !out || n_params != NPARAM || !(std::isfinite(in_scale) && in_scale > 0.0f)) {
-        set_error("msf_cnn_create: need 15169 parameters and a positive input scale");
+    if (!params || !out || !scales || n_params != NPARAM) {
+        set_error("msf_cnn_create: need 15169 parameters and 3 scales");
         return MSF_EINVAL;
     }
+    for (int k = 0; k < 3; ++k)
+        if (!(std::isfinite(scales[k]) && scales[k] > 0.0f)) {
+            set_error("msf_cnn_create: scales must be positive and finite");
+            return MSF_EINVAL;
+        }
     for (int64_t i = 0; i < n_params; ++i)
         if (!std::isfinite(params[i])) { set_error("msf_cnn_create: non-finite parameter"); return MSF_EINVAL; }
     msf_cnn *C = new (std::nothrow) msf_cnn();
     if (!C) { set_error("host allocation failed"); return MSF_ENOMEM; }
-    C->c = in_scale;
+    C->cv = scales[0];
+    C->cg = scales[1];
+    C->co = scales[2];
     hipError_t e = hipSuccess;
     auto fail = [&](hipError_t err) {
         msf_cnn_destroy(C);
@@ -480,7 +488,7 @@ msf_status msf_cnn_train_step(msf_cnn *C, const float *v, const float *g, const 
     CHK(cnn_reserve(C, nvox));
     CHK(cnn_forward(C, v, g, n, nz, ny, nx, C->pred, s));
     const unsigned lb = grid_of(nvox, 256);
-    hipLaunchKernelGGL(k_mse, dim3(lb), dim3(256), 0, s, C->pred, target, nvox, C->c, C->ga, C->lpart);
+    hipLaunchKernelGGL(k_mse, dim3(lb), dim3(256), 0, s, C->pred, target, nvox, C->co, C->ga, C->lpart);
     CHK(hipGetLastError());
     // backward: g_l is the gradient at layer l's output (bf16, ReLU mask applied)
     uint16_t *gcur = C->ga, *gnext = C->gb;

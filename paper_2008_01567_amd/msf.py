@@ -52,7 +52,8 @@ class msf_solve_opts(C.Structure):
 class msf_solve_stats(C.Structure):
     _fields_ = [("iters", C.POINTER(C.c_int32)), ("rel_residual", C.POINTER(C.c_double)),
                 ("true_rel_residual", C.POINTER(C.c_double)), ("converged", C.POINTER(C.c_uint8)),
-                ("cnn_used", C.POINTER(C.c_uint8)), ("steps", C.c_int32), ("reserved", C.c_int32),
+                ("cnn_used", C.POINTER(C.c_uint8)), ("start_rel_residual", C.POINTER(C.c_double)),
+                ("steps", C.c_int32), ("reserved", C.c_int32),
                 ("seconds", C.c_double)]
 
 
@@ -95,7 +96,7 @@ def lib():
         L.msf_plan_get_timing.argtypes = [vp, C.POINTER(msf_timing)]
         L.msf_count_intersections.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.msf_prox_features.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
-        L.msf_cnn_create.argtypes = [C.POINTER(C.c_float), C.c_int64, C.c_float, C.POINTER(vp)]
+        L.msf_cnn_create.argtypes = [C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_float), C.POINTER(vp)]
         L.msf_cnn_destroy.argtypes = [vp]
         L.msf_cnn_get_params.argtypes = [vp, C.POINTER(C.c_float)]
         L.msf_cnn_infer.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp]
@@ -237,14 +238,17 @@ class Plan:
         trel = np.zeros(nf)
         conv = np.zeros(nf, dtype=np.uint8)
         used = np.zeros(nf, dtype=np.uint8)
+        rel0 = np.zeros(nf)
         st = msf_solve_stats(iters.ctypes.data_as(C.POINTER(C.c_int32)), rel.ctypes.data_as(C.POINTER(C.c_double)),
                              trel.ctypes.data_as(C.POINTER(C.c_double)), conv.ctypes.data_as(C.POINTER(C.c_uint8)),
-                             used.ctypes.data_as(C.POINTER(C.c_uint8)), 0, 0, 0.0)
+                             used.ctypes.data_as(C.POINTER(C.c_uint8)), rel0.ctypes.data_as(C.POINTER(C.c_double)),
+                             0, 0, 0.0)
         status = _check(lib().msf_prox_solve(self._h, _ptr(v, self.n_vox), _ptr(y, self.n_meas),
                                              _ptr(lam, self.n_meas), float(sigma), C.byref(o),
                                              _ptr(out, self.n_vox), C.byref(st), _stream(stream)))
         return out, {"status": status, "iters": iters, "rel_residual": rel, "true_rel_residual": trel,
-                     "converged": conv.astype(bool), "cnn_used": used.astype(bool), "steps": st.steps,
+                     "converged": conv.astype(bool), "cnn_used": used.astype(bool), "start_rel_residual": rel0,
+                     "steps": st.steps,
                      "seconds": st.seconds}
 
 
@@ -253,14 +257,16 @@ N_CNN_PARAMS = 15169
 
 class Cnn:
     """The warm-start network (msf_cnn_*).  params: FP32 [15169] (per layer
-    W[out][in][3][3][3] then b[out]); in_scale: the input scale c."""
+    W[out][in][3][3][3] then b[out]); scales: c or (c_v, c_g, c_o)."""
 
-    def __init__(self, params, in_scale):
+    def __init__(self, params, scales):
         p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        sc = np.full(3, scales, dtype=np.float32) if np.isscalar(scales) else np.asarray(scales, dtype=np.float32)
         h = C.c_void_p()
-        _check(lib().msf_cnn_create(p.ctypes.data_as(C.POINTER(C.c_float)), p.size, float(in_scale), C.byref(h)))
+        _check(lib().msf_cnn_create(p.ctypes.data_as(C.POINTER(C.c_float)), p.size,
+                                    sc.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
         self._h = h
-        self.in_scale = float(in_scale)
+        self.scales = tuple(float(x) for x in sc)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -50,7 +50,7 @@ def _inputs(seed):
 def test_forward_matches_oracle(msf):
     params = _params(0)
     v, g, _ = _inputs(1)
-    c = 0.05
+    c = (0.05, 0.01, 0.02)
     net = msf.Cnn(ocnn.flatten(params), c)
     got = net.infer(_dev(v), _dev(g)).cpu().numpy()
     inp = np.stack([v, g], axis=1).astype(np.float64)
@@ -63,7 +63,7 @@ def test_forward_matches_oracle(msf):
 def test_gradients_match_oracle(msf):
     params = _params(2)
     v, g, t = _inputs(3)
-    c = 0.05
+    c = (0.05, 0.01, 0.02)
     net = msf.Cnn(ocnn.flatten(params), c)
     loss, grad = net.train_step(_dev(v), _dev(g), _dev(t), lr=0.0, apply=False, want_grad=True)
     inp = np.stack([v, g], axis=1).astype(np.float64)

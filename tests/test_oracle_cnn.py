@@ -68,14 +68,15 @@ def test_network_gradients_match_autograd():
 
 
 def test_scaled_network_matches_unscaled_definition():
-    """x0 = v + c f(v/c, g/c): the scale only rescales the inputs and the output."""
+    """x0 = v + c_o f(v/c_v, g/c_g): the scales only rescale the inputs and the output."""
     rng = np.random.default_rng(8)
     params = _rand_params(9)
     inp = rng.standard_normal((1, 2, 4, 5, 6))
-    c = 0.05
-    a, _ = cnn.forward(params, inp, scale=c)
-    b, _ = cnn.forward(params, inp / c)
-    assert np.allclose(a, inp[:, 0:1] + c * (b - inp[:, 0:1] / c), rtol=1e-12, atol=1e-14)
+    cv, cg, co = 0.05, 0.002, 0.01
+    a, _ = cnn.forward(params, inp, scale=(cv, cg, co))
+    scaled = np.concatenate([inp[:, 0:1] / cv, inp[:, 1:2] / cg], axis=1)
+    b, _ = cnn.forward(params, scaled)
+    assert np.allclose(a, inp[:, 0:1] + co * (b - scaled[:, 0:1]), rtol=1e-12, atol=1e-14)
 
 
 def test_bf16_backward_rounds_at_the_documented_points():
