@@ -193,6 +193,50 @@ msf_status msf_cnn_train_step(msf_cnn *cnn, const float *v, const float *g, cons
                               int32_t nz, int32_t ny, int32_t nx, double lr, int32_t apply, double *loss_out,
                               float *grad_out, void *stream);
 
+/* ---- multi-agent consensus equilibrium around the proximal map ----
+ * Algorithm 1 of the paper (partial-update Mann iteration, Sec. III):
+ *     X <- F~(W; X);  Z <- G(2X - W);  W <- W + 2 rho (Z - X);  output X_0,
+ * with F~ = [L~(W_0; X_0), H_1(W_1), H_2(W_2), H_3(W_3)] and G the weighted
+ * average W_0/(1+beta) + beta/(1+beta) mean_k W_k (eqs. (mace_G), (mace_avg)).
+ * L~ is msf_prox_solve on W_0 started from the previous X_0: to tol (full
+ * proximal map, partial_iters = 0) or for partial_iters CG steps (the paper's
+ * partial update).  The paper's CNN denoisers are not available; the prior
+ * agents are stand-ins that are proximal maps: MSF_PRIOR_PLANE_GAUSS = the
+ * symmetric Gaussian smoother (std prior_param voxels, 7 taps, zero outside)
+ * within the xy, yz and zx planes; MSF_PRIOR_RIDGE = x / (1 + prior_param
+ * sigma^2), the proximal map of (prior_param / 2) ||x||^2. */
+enum { MSF_PRIOR_PLANE_GAUSS = 0, MSF_PRIOR_RIDGE = 1 };
+
+typedef struct msf_mace_opts {
+    int32_t n_iter;              /* Mann iterations (10 in the paper's experiments) */
+    int32_t prior;               /* MSF_PRIOR_PLANE_GAUSS or MSF_PRIOR_RIDGE */
+    int32_t partial_iters;       /* 0: full solves; k > 0: k CG steps per outer iteration */
+    int32_t max_iter;            /* CG step cap of a full solve */
+    double beta;                 /* prior weight (1 = equal weighting) */
+    double rho;                  /* Mann parameter in (0, 1); 0.5 = consensus ADMM */
+    double prior_param;          /* Gaussian std (voxels) or ridge lambda */
+    double tol;                  /* relative residual of a full solve */
+    const msf_cnn *cnn;          /* optional learned start of the first solve */
+} msf_mace_opts;
+
+typedef struct msf_mace_stats {
+    int64_t *cg_iters;           /* host [capacity] or NULL: CG steps summed over frames, per outer iteration */
+    int32_t capacity;
+    int32_t reserved;
+    int64_t cg_total;            /* out */
+    double seconds;              /* out */
+} msf_mace_stats;
+
+void msf_mace_opts_default(msf_mace_opts *opts);
+
+/* Runs the MACE loop on the plan's 4D volume.  x_init: device volume (the
+ * initial reconstruction x^(0)) or NULL for zeros; y, lambda: device
+ * sinograms; x_out: device volume (the final X_0).  Allocates 9 volumes of
+ * workspace for the call.  Returns MSF_NOT_CONVERGED if a full solve hit
+ * max_iter. */
+msf_status msf_mace_run(msf_plan *plan, const float *x_init, const float *y, const float *lambda, double sigma,
+                        const msf_mace_opts *opts, float *x_out, msf_mace_stats *stats, void *stream);
+
 /* Live kernel timing.  While enabled, msf_prox_solve records HIP events on
  * the caller's stream around every forward-projector and backprojector launch
  * of its CG steps (also inside captured graphs) and accumulates the elapsed

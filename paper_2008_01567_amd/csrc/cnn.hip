@@ -395,9 +395,18 @@ hipError_t cnn_io_buffers(msf_cnn *C, int64_t n, float **g, float **x)
 hipError_t cnn_infer_internal(msf_cnn *C, const float *v, const float *g, int N, int Z, int Y, int X, float *x0,
                               hipStream_t s)
 {
-    hipError_t e = cnn_reserve(C, (int64_t)N * Z * Y * X);
+    // volumes are independent: evaluate them in chunks of at most 2^26 voxels
+    // (activations take 32 bytes per voxel and layer)
+    const int64_t per = (int64_t)Z * Y * X;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)1 << 26) / per));
+    hipError_t e = cnn_reserve(C, (int64_t)chunk * per);
     if (e != hipSuccess) return e;
-    return cnn_forward(C, v, g, N, Z, Y, X, x0, s);
+    for (int f0 = 0; f0 < N; f0 += chunk) {
+        const int nf = std::min(chunk, N - f0);
+        e = cnn_forward(C, v + f0 * per, g + f0 * per, nf, Z, Y, X, x0 + f0 * per, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 extern "C" {

@@ -57,6 +57,20 @@ class msf_solve_stats(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class msf_mace_opts(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("prior", C.c_int32), ("partial_iters", C.c_int32), ("max_iter", C.c_int32),
+                ("beta", C.c_double), ("rho", C.c_double), ("prior_param", C.c_double), ("tol", C.c_double),
+                ("cnn", C.c_void_p)]
+
+
+class msf_mace_stats(C.Structure):
+    _fields_ = [("cg_iters", C.POINTER(C.c_int64)), ("capacity", C.c_int32), ("reserved", C.c_int32),
+                ("cg_total", C.c_int64), ("seconds", C.c_double)]
+
+
+MSF_PRIOR_PLANE_GAUSS, MSF_PRIOR_RIDGE = 0, 1
+
+
 class msf_timing(C.Structure):
     _fields_ = [("forward_ms", C.c_double), ("forward_launches", C.c_int64), ("back_ms", C.c_double),
                 ("back_launches", C.c_int64)]
@@ -69,7 +83,7 @@ EXPORTS = ["msf_solve_opts_default", "msf_plan_create", "msf_plan_destroy", "msf
            "msf_plan_get_tiles", "msf_plan_sizes", "msf_project", "msf_backproject", "msf_prox_solve",
            "msf_last_error", "msf_version", "msf_plan_set_timing", "msf_plan_get_timing",
            "msf_count_intersections", "msf_prox_features", "msf_cnn_create", "msf_cnn_destroy",
-           "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step"]
+           "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step", "msf_mace_opts_default", "msf_mace_run"]
 
 
 def lib():
@@ -96,6 +110,9 @@ def lib():
         L.msf_plan_get_timing.argtypes = [vp, C.POINTER(msf_timing)]
         L.msf_count_intersections.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.msf_prox_features.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
+        L.msf_mace_opts_default.argtypes = [C.POINTER(msf_mace_opts)]
+        L.msf_mace_run.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(msf_mace_opts), vp,
+                                   C.POINTER(msf_mace_stats), vp]
         L.msf_cnn_create.argtypes = [C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_float), C.POINTER(vp)]
         L.msf_cnn_destroy.argtypes = [vp]
         L.msf_cnn_get_params.argtypes = [vp, C.POINTER(C.c_float)]
@@ -104,7 +121,7 @@ def lib():
                                          C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_float), vp]
         for name in EXPORTS:
             if name not in ("msf_last_error", "msf_version", "msf_plan_destroy", "msf_solve_opts_default",
-                            "msf_cnn_destroy"):
+                            "msf_cnn_destroy", "msf_mace_opts_default"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -215,6 +232,24 @@ class Plan:
         _check(lib().msf_prox_features(self._h, _ptr(v, self.n_vox), _ptr(y, self.n_meas), _ptr(lam, self.n_meas),
                                        float(sigma), _ptr(out, self.n_vox), _stream(stream)))
         return out
+
+    def mace(self, y, lam, sigma, x_init=None, n_iter=10, prior=MSF_PRIOR_PLANE_GAUSS, prior_param=1.0, beta=1.0,
+             rho=0.5, partial_iters=0, tol=1e-6, max_iter=2000, cnn=None, out=None, stream=None):
+        """Algorithm 1 (msf_mace_run); returns (X_0, stats)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=torch.float32, device=y.device)
+        o = msf_mace_opts()
+        lib().msf_mace_opts_default(C.byref(o))
+        o.n_iter, o.prior, o.partial_iters, o.max_iter = int(n_iter), int(prior), int(partial_iters), int(max_iter)
+        o.beta, o.rho, o.prior_param, o.tol = float(beta), float(rho), float(prior_param), float(tol)
+        o.cnn = cnn._h.value if cnn is not None else None
+        it = np.zeros(max(n_iter, 1), dtype=np.int64)
+        st = msf_mace_stats(it.ctypes.data_as(C.POINTER(C.c_int64)), len(it), 0, 0, 0.0)
+        xi = _ptr(x_init, self.n_vox) if x_init is not None else None
+        status = _check(lib().msf_mace_run(self._h, xi, _ptr(y, self.n_meas), _ptr(lam, self.n_meas), float(sigma),
+                                           C.byref(o), _ptr(out, self.n_vox), C.byref(st), _stream(stream)))
+        return out, {"status": status, "cg_iters": it[:n_iter], "cg_total": st.cg_total, "seconds": st.seconds}
 
     def prox_solve(self, v, y, lam, sigma, tol=1e-6, max_iter=1000, check_every=8, x0=None, use_graph=True,
                    true_residual=False, out=None, stream=None, cnn=None):

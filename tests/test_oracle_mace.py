@@ -45,3 +45,23 @@ def test_ridge_agents_reach_map_solution():
     assert np.linalg.norm(xbar - want) <= 1e-6 * np.linalg.norm(want)
     # at equilibrium every agent's output equals the consensus value
     assert np.linalg.norm(xs - want) <= 1e-6 * np.linalg.norm(want)
+
+
+def test_plane_smoothers_are_proximal_maps():
+    """Symmetric (<Hx, z> = <x, Hz>) with eigenvalues in (0, 1]: the proximal map of a
+    convex quadratic (a linear map is a proximal map iff it is symmetric with spectrum in [0, 1])."""
+    rng = np.random.default_rng(1)
+    shape = (1, 5, 6, 7)
+    n = int(np.prod(shape))
+    for k in (1, 2, 3):
+        H = np.zeros((n, n))
+        for j in range(n):
+            e = np.zeros(n)
+            e[j] = 1.0
+            H[:, j] = mace.plane_smoother(e.reshape(shape), k, 1.0).reshape(-1)
+        assert np.allclose(H, H.T, atol=1e-15)
+        ev = np.linalg.eigvalsh(H)
+        assert ev.min() > 0.0 and ev.max() <= 1.0 + 1e-12
+    # a constant field away from the boundary is preserved (taps sum to one)
+    x = np.ones((1, 9, 9, 9))
+    assert abs(mace.plane_smoother(x, 1, 1.0)[0, 4, 4, 4] - 1.0) < 1e-14
