@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="time plain batched CG only")
     ap.add_argument("--cpu-iters", type=int, default=40, help="FP64 CG iterations timed in the CPU sample")
-    ap.add_argument("--tiles", default="", help="rays_per_lane,waves_per_group,xcd_remap (default: plan default)")
+    ap.add_argument("--tiles", default="", help="rays_per_lane,waves_per_group,back_mode,xcd_remap (default: autotune)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default launch shape")
     return ap.parse_args()
 
 
@@ -98,8 +99,11 @@ def main():
     v_np = synth.make_v(cfg, x0.astype(np.float64)).astype(np.float32)
     plan = msf.Plan(geom)
     if args.tiles:
-        r, w, xr = (int(t) for t in args.tiles.split(","))
-        plan.set_tiles(rays_per_lane=r, waves_per_group=w, back_mode=0, xcd_remap=xr)
+        r, w, b, xr = (int(t) for t in args.tiles.split(","))
+        plan.set_tiles(rays_per_lane=r, waves_per_group=w, back_mode=b, xcd_remap=xr)
+    elif not args.no_autotune:
+        t1 = time.perf_counter()
+        log("autotune: %s (%.1fs)" % (plan.autotune(), time.perf_counter() - t1))
     y_clean = plan.project(torch.from_numpy(x0).to(dev)).cpu().numpy()
     eps = synth.noise_eps(cfg, geom, dtype=np.float32)
     y_np, lam_np = synth.finish_measurement(y_clean, eps, synth.frame_counts(geom), geom.n_rays_per_view,

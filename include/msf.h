@@ -138,8 +138,15 @@ void msf_plan_destroy(msf_plan *plan);
 msf_status msf_plan_set_tiles(msf_plan *plan, const msf_tiles *tiles);
 msf_status msf_plan_get_tiles(const msf_plan *plan, msf_tiles *tiles);
 
-/* Number of nonzeros of A (ray-voxel intersections) is not stored; the
- * per-plan sizes are reported here (host outputs, any may be NULL). */
+/* Autotuner: times the forward projector and both adjoints (HIP events on
+ * the given stream, plan-owned buffers) for every supported launch shape on
+ * this plan's geometry and applies the fastest (forward + adjoint) pair.
+ * cache_path (may be NULL): text file of "key tiles" lines, key = GPU arch +
+ * geometry sizes + a hash of the angle list; a hit is applied without timing,
+ * a miss is appended.  chosen (host, may be NULL) receives the shape. */
+msf_status msf_plan_autotune(msf_plan *plan, const char *cache_path, msf_tiles *chosen, void *stream);
+
+/* Per-plan sizes (host outputs, any may be NULL). */
 msf_status msf_plan_sizes(const msf_plan *plan, int64_t *n_vox_total, int64_t *n_meas_total,
                           int64_t *workspace_bytes);
 
@@ -245,7 +252,8 @@ msf_status msf_mace_run(msf_plan *plan, const float *x_init, const float *y, con
 typedef struct msf_timing {
     double forward_ms;           /* summed duration of the timed forward-projector launches */
     int64_t forward_launches;
-    double back_ms;              /* summed duration of the timed backprojector launches */
+    double back_ms;              /* summed duration of the timed backprojector launches (with the
+                                    voxel-driven adjoint this kernel also applies the CG update of x, r) */
     int64_t back_launches;
 } msf_timing;
 msf_status msf_plan_set_timing(msf_plan *plan, int32_t enable);

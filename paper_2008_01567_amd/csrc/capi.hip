@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 #include <new>
 
 int64_t vol_chunk();
@@ -30,7 +31,7 @@ void free_plan_memory(msf_plan *P)
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     P->graph = nullptr;
     P->graph_valid = false;
-    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
+    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
                     P->sy, P->slam, P->sz, P->part_proj, P->part_vol, P->scal, P->iscal, P->consts,
                     P->flags};
     for (void *q : ptrs)
@@ -98,11 +99,16 @@ msf_status setup_tiles(msf_plan &P)
     hipError_t e;
     if (P.d_tile_offset) (void)hipFree(P.d_tile_offset);
     if (P.part_proj) (void)hipFree(P.part_proj);
+    if (P.part_g) (void)hipFree(P.part_g);
     P.d_tile_offset = nullptr;
     P.part_proj = nullptr;
+    P.part_g = nullptr;
     int64_t dummy = 0;
     if ((e = dalloc(&P.d_tile_offset, P.nf + 1, dummy)) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = dalloc(&P.part_proj, (size_t)total, dummy)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    // workgroup partials of the fused gather + CG update (same tiling as launch_back_gather)
+    P.part_g_per_frame = P.proj_params(false).g_tiles_per_frame;
+    if ((e = dalloc(&P.part_g, (size_t)(P.part_g_per_frame * P.nf), dummy)) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMemcpy(P.d_tile_offset, P.tile_offset.data(), sizeof(int64_t) * (P.nf + 1),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "hipMemcpy");
@@ -230,7 +236,23 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
     std::vector<double2> rzp(P->nv);
     for (int iv = 0; iv < P->nv; ++iv) {
         const double zp = (iv - 0.5 * (P->nv - 1)) * P->dv + P->offv;
-        rzp[iv] = make_double2(zp, zp != 0.0 ? 1.0 / zp : 0.0);
+        // a huge finite 1/zp for the level ray lets the adjoint use one crossing formula for every row
+        rzp[iv] = make_double2(zp, zp != 0.0 ? 1.0 / zp : 1e290);
+    }
+    // 3D length per unit of xy length of the ray of pixel (u, v): sqrt(1 + (zp / lxy)^2), lxy = |pixel - source|_xy
+    if ((e = dalloc(&P->d_scale, (size_t)P->nu * P->nv, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    {
+        std::vector<float> sc((size_t)P->nu * P->nv);
+        for (int iu = 0; iu < P->nu; ++iu) {
+            const double u = (iu - 0.5 * (P->nu - 1)) * P->du + P->offu;
+            const double lxy = std::sqrt(P->rsd * P->rsd + u * u);
+            for (int iv = 0; iv < P->nv; ++iv) {
+                const double m = rzp[iv].x / lxy;
+                sc[(size_t)iu * P->nv + iv] = (float)std::sqrt(1.0 + m * m);
+            }
+        }
+        if ((e = hipMemcpy(P->d_scale, sc.data(), sizeof(float) * sc.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_fail(e, "hipMemcpy"));
     }
     if ((e = hipMemcpy(P->d_rzp, rzp.data(), sizeof(double2) * P->nv, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(hip_fail(e, "hipMemcpy"));
@@ -292,6 +314,102 @@ msf_status msf_plan_set_tiles(msf_plan *P, const msf_tiles *t)
     return st;
 }
 
+msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *chosen, void *stream)
+{
+    g_err.clear();
+    if (!P) { set_error("null plan"); return MSF_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    // geometry key: sizes, distances and a hash of the angle list
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *d, size_t n) {
+        const unsigned char *c = (const unsigned char *)d;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    mix(P->view_offset.data(), P->view_offset.size() * sizeof(int64_t));
+    mix(P->angles.data(), P->angles.size() * sizeof(double));
+    char key[512];
+    snprintf(key, sizeof(key), "%s %d %d %d %d %d %d %.6g %.6g %.6g %.6g %.6g %.6g %016llx", prop.gcnArchName, P->nx,
+             P->ny, P->nz, P->nf, P->nu, P->nv, P->du, P->dv, P->rs, P->rsd, P->offu, P->offv, (unsigned long long)h);
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "r")) {
+            char line[768];
+            while (fgets(line, sizeof(line), f)) {
+                const size_t kl = strlen(key);
+                msf_tiles t{};
+                if (strncmp(line, key, kl) == 0 &&
+                    sscanf(line + kl, " %d %d %d %d", &t.rays_per_lane, &t.waves_per_group, &t.back_mode,
+                           &t.xcd_remap) == 4 && tiles_ok(t)) {
+                    fclose(f);
+                    msf_status st = msf_plan_set_tiles(P, &t);
+                    if (st == MSF_OK && chosen) *chosen = t;
+                    return st;
+                }
+            }
+            fclose(f);
+        }
+    }
+    // time every shape on a fixed pseudo-random volume (internal buffers)
+    HIPCHK(launch_fill(P->p, P->nvox_total, 0.01f, s));
+    HIPCHK(launch_fill(P->slam, P->nmeas_total, 1.0f, s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_it = [&](auto &&fn) -> float {
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess || fn() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess)
+                return 1e30f;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) best = std::min(best, ms);   // first run warms caches and code
+        }
+        return best;
+    };
+    const msf_tiles old = P->tiles;
+    msf_tiles best = old;
+    float best_t = 1e30f;
+    const int R[] = {1, 2, 3, 4, 6}, W[] = {1, 2, 4};
+    const int need = (P->iv_hi - P->iv_lo + 64) / 64;
+    for (int xr = 0; xr <= 1; ++xr)
+        for (int w : W)
+            for (int r : R) {
+                if (r > std::max(need, 1) + 1) continue;   // more rays per lane than rows: idle lanes
+                msf_tiles t{r, w, 1, xr};
+                P->tiles = t;
+                if (setup_tiles(*P) != MSF_OK) continue;
+                const float tf = time_it([&] { return launch_forward(*P, PM_WEIGHTED, P->p, nullptr, P->sz, false, s); });
+                const float tg = time_it([&] { return launch_back(*P, P->sz, P->bp, false, s); });
+                P->tiles.back_mode = 0;
+                const float ts = time_it([&] {
+                    hipError_t e = launch_fill_d(P->bp, P->nvox_total, s);
+                    return e != hipSuccess ? e : launch_back(*P, P->sz, P->bp, false, s);
+                });
+                if (tf + tg < best_t) { best_t = tf + tg; best = t; best.back_mode = 1; }
+                if (tf + ts < best_t) { best_t = tf + ts; best = t; best.back_mode = 0; }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(launch_fill_d(P->bp, P->nvox_total, s));   // the solver expects a cleared accumulator
+    P->tiles = best;
+    msf_status st = setup_tiles(*P);
+    if (st != MSF_OK) return st;
+    HIPCHK(hipStreamSynchronize(s));
+    if (chosen) *chosen = best;
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "a")) {
+            fprintf(f, "%s %d %d %d %d\n", key, best.rays_per_lane, best.waves_per_group, best.back_mode, best.xcd_remap);
+            fclose(f);
+        }
+    }
+    (void)old;
+    return MSF_OK;
+}
+
 msf_status msf_plan_get_tiles(const msf_plan *P, msf_tiles *t)
 {
     if (!P || !t) { set_error("null argument"); return MSF_EINVAL; }
@@ -327,6 +445,7 @@ msf_status msf_backproject(msf_plan *P, const float *y, float *x, void *stream)
     if (!P || !x || !y) { set_error("null argument"); return MSF_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(sino_to_internal(*P, y, P->sz, 0, nullptr, s));
+    HIPCHK(launch_prescale(*P, P->sz, s));
     HIPCHK(launch_fill_d(P->bp, P->nvox_total, s));
     HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
     HIPCHK(launch_d2f(P->bp, P->p, P->nvox_total, s));
@@ -404,7 +523,7 @@ msf_status prepare(msf_plan *P, const float *v, const float *y, const float *lam
         return MSF_EINVAL;
     }
     // ||b|| with b = A^T Lambda y + v / sigma^2
-    HIPCHK(launch_sino_mul(P->slam, P->sy, P->sz, P->nmeas_total, s));
+    HIPCHK(launch_sino_mul_scaled(P->slam, P->sy, P->d_scale, (int64_t)P->nu * P->nv, P->sz, P->nmeas_total, s));
     HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
     HIPCHK(launch_vol_bnorm(*P, s));
     HIPCHK(launch_scalar_reduce(*P, RW_BNORM, s));

@@ -5,11 +5,12 @@
 // Vectors are FP32 in HBM; every inner product, step size and residual norm
 // is FP64.  Vector updates are evaluated in FP64 and rounded once to FP32.
 //
-// One CG step for all frames is six launches:
+// One CG step for all frames is six launches (five with the voxel-driven adjoint):
 //   forward   w = A p, z = Lambda w, partial <w, Lambda w>   (projector.hip)
 //   alpha     <p, H p> = <w, Lambda w> + ||p||^2 / sigma^2, alpha = gamma / <p, H p>
 //   back      q' = A^T z (scatter into a zeroed buffer)
 //   update    x += alpha p, r -= alpha (q' + p / sigma^2), q' = 0, partial ||r||^2
+//             (with the voxel-driven adjoint, back and update are one kernel and q' stays in registers)
 //   beta      gamma' = ||r||^2, convergence test, beta = gamma' / gamma
 //   direction p = r + beta p, partial ||p||^2
 // Per-frame FP64 partial sums are written per workgroup and reduced in a
@@ -88,6 +89,14 @@ __global__ void k_copy(float *__restrict__ d, const float *__restrict__ s, int64
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         d[i] = s[i];
+}
+
+// o = a * b * scale[i mod per_view]  (Lambda y pre-multiplied by the ray length factor for the adjoint)
+__global__ void k_mul_scaled(const float *__restrict__ a, const float *__restrict__ b, const float *__restrict__ sc,
+                             int64_t per_view, float *__restrict__ o, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        o[i] = (float)((double)a[i] * (double)b[i] * (double)sc[i % per_view]);
 }
 
 __global__ void k_mul(const float *__restrict__ a, const float *__restrict__ b, float *__restrict__ o, int64_t n)
@@ -256,6 +265,8 @@ __global__ __launch_bounds__(VB) void k_update_p(VolArgs A)
 struct ScalArgs {
     int64_t nvox;
     const double *part_vol;     // [nf * bpf]
+    const double *part_beta;    // partials of ||r||^2 after the x, r update: [nf * bpf_beta]
+    int64_t bpf_beta;
     const double *part_proj;    // [total tiles]
     const int64_t *tile_offset; // [nf + 1]
     double *scal;               // [SC_COUNT][nf]
@@ -337,7 +348,7 @@ __global__ __launch_bounds__(VB) void k_red_beta(ScalArgs A)
 {
     const int f = blockIdx.x;
     if (!I(A, IS_ACTIVE, f)) return;
-    const double g = frame_sum(A.part_vol, (int64_t)f * A.bpf, (int64_t)(f + 1) * A.bpf);
+    const double g = frame_sum(A.part_beta, (int64_t)f * A.bpf_beta, (int64_t)(f + 1) * A.bpf_beta);
     if (threadIdx.x != 0) return;
     const double bn = S(A, SC_BNORM, f);
     const double rel = bn > 0.0 ? sqrt(g) / bn : sqrt(g);
@@ -368,11 +379,13 @@ VolArgs vol_args(msf_plan &P, bool with_active)
     return A;
 }
 
-ScalArgs scal_args(msf_plan &P)
+ScalArgs scal_args(msf_plan &P, bool fused = false)
 {
     ScalArgs A;
     A.nvox = P.nvox;
     A.part_vol = P.part_vol;
+    A.part_beta = fused ? P.part_g : P.part_vol;
+    A.bpf_beta = fused ? P.part_g_per_frame : P.vol_blocks_per_frame;
     A.part_proj = P.part_proj;
     A.tile_offset = P.d_tile_offset;
     A.scal = P.scal;
@@ -419,6 +432,14 @@ hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sino_mul_scaled(const float *a, const float *b, const float *scale, int64_t per_view, float *out,
+                                  int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mul_scaled, dim3(grid_for(n)), dim3(256), 0, s, a, b, scale, per_view, out, n);
     return hipGetLastError();
 }
 
@@ -482,17 +503,24 @@ hipError_t launch_scalar_reduce(msf_plan &P, int what, hipStream_t s)
 hipError_t launch_cg_step(msf_plan &P, hipStream_t s, hipEvent_t *ev)
 {
     hipError_t e;
+    // the voxel-driven adjoint finishes the x, r update in its epilogue
+    const bool fused = P.tiles.back_mode == 1;
     if (ev && (e = hipEventRecordWithFlags(ev[0], s, hipEventRecordExternal)) != hipSuccess) return e;
     if ((e = launch_forward(P, PM_WEIGHTED, P.p, nullptr, P.sz, true, s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecordWithFlags(ev[1], s, hipEventRecordExternal)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_red_alpha, dim3(P.nf), dim3(VB), 0, s, scal_args(P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecordWithFlags(ev[2], s, hipEventRecordExternal)) != hipSuccess) return e;
-    if ((e = launch_back(P, P.sz, P.bp, true, s)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecordWithFlags(ev[3], s, hipEventRecordExternal)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_update_xr, vol_grid(P), dim3(VB), 0, s, vol_args(P, true));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_red_beta, dim3(P.nf), dim3(VB), 0, s, scal_args(P));
+    if (fused) {
+        if ((e = launch_back_gather_update(P, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecordWithFlags(ev[3], s, hipEventRecordExternal)) != hipSuccess) return e;
+    } else {
+        if ((e = launch_back(P, P.sz, P.bp, true, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecordWithFlags(ev[3], s, hipEventRecordExternal)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_update_xr, vol_grid(P), dim3(VB), 0, s, vol_args(P, true));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_red_beta, dim3(P.nf), dim3(VB), 0, s, scal_args(P, fused));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_update_p, vol_grid(P), dim3(VB), 0, s, vol_args(P, true));
     return hipGetLastError();

@@ -41,12 +41,16 @@ struct ProjParams {
     int xcd_remap;
     int64_t nvox;                // voxels per frame
     int64_t total_tiles;
-    const double2 *rzp;          // [nv] (height zp of detector row v, 1/zp or 0 when zp = 0)
+    const double2 *rzp;          // [nv] (height zp of detector row v, 1/zp; 1e290 when zp = 0)
     // voxel-driven backprojector
     const struct ColEntry *cols; // [n_views * nu] column table
     int64_t g_tiles_per_frame;
     int g_zpl;                   // z voxels per lane
+    const float *scale;          // [nu][nv] 3D ray length per unit of xy length: sqrt(1 + (zp / lxy)^2)
 };
+
+// The sinogram a backprojector reads is pre-multiplied by the ray's 3D length
+// factor (the scale table), so the adjoint kernels never recompute it.
 
 // One detector column's xy line (shared by all its rows), as the forward
 // projector computes it; the voxel-driven backprojector reads it from a table
@@ -91,6 +95,9 @@ struct msf_plan {
     // device tables
     double2 *d_cs = nullptr;
     double2 *d_rzp = nullptr;             // [nv]
+    float *d_scale = nullptr;             // [nu][nv]
+    double *part_g = nullptr;             // [nf * gather tiles per frame] ||r||^2 partials of the fused gather
+    int64_t part_g_per_frame = 0;
     ColEntry *d_cols = nullptr;           // [n_views * nu]
     int64_t *d_view_offset = nullptr;
     int64_t *d_tile_offset = nullptr;
@@ -139,6 +146,11 @@ hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_
 // A^T into the FP64 accumulator with the plan's back_mode (scatter adds into a
 // zeroed buffer; gather overwrites every voxel of the frames it processes)
 hipError_t launch_back(const msf_plan &P, const float *sino, double *vol, bool with_active, hipStream_t s);
+// voxel-driven A^T fused with the CG update of x and r (partials of ||r||^2 in part_g)
+hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s);
+// sino[i] *= scale[i mod (nu nv)] (internal layout)
+hipError_t launch_prescale(const msf_plan &P, float *sino, hipStream_t s);
+hipError_t launch_scale_table(msf_plan &P, hipStream_t s);
 hipError_t launch_col_table(msf_plan &P, hipStream_t s);
 
 // batched transpose [B][R][C] -> [B][C][R]; counts entries failing the check
@@ -152,6 +164,9 @@ hipError_t launch_fill_d(double *p, int64_t n, hipStream_t s);
 hipError_t launch_d2f(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_sino_mul(const float *a, const float *b, float *out, int64_t n, hipStream_t s);
+// out = a * b * scale[i mod per_view]
+hipError_t launch_sino_mul_scaled(const float *a, const float *b, const float *scale, int64_t per_view, float *out,
+                                  int64_t n, hipStream_t s);
 hipError_t launch_vol_bnorm(msf_plan &P, hipStream_t s);
 hipError_t launch_vol_init_residual(msf_plan &P, hipStream_t s);
 hipError_t launch_vol_true_residual(msf_plan &P, hipStream_t s);

@@ -24,11 +24,17 @@
 // line's closest approach to the rotation axis (|s| <= half the volume
 // diagonal), which keeps FP32 parameters small.
 //
-// The adjoint (scatter) runs the very same traversal and adds
-// length * value into each voxel with hardware FP64 atomics (an FP64
-// accumulator keeps the mixed-sign sums of CG free of FP32 cancellation), so
-// A and A^T use bit-identical lengths: the adjoint is exact up to summation
-// order.
+// A piece's 3D length is its xy length times sqrt(1 + (zp / lxy)^2), a factor
+// of the ray alone (detector column u and row v; the same for every view):
+// the forward applies it to the finished ray sum from a [nu][nv] table, and
+// the adjoints read sinograms that are already multiplied by it.
+//
+// The adjoint comes in two forms that use bit-identical lengths.  The scatter
+// runs the very same traversal and adds length * value into each voxel with
+// hardware FP64 atomics (an FP64 accumulator keeps the mixed-sign sums of CG
+// free of FP32 cancellation).  The gather (the default) is voxel-driven,
+// deterministic and atomic-free; it recomputes each piece with the forward
+// walk's crossing expressions.
 #include "msf_internal.h"
 
 #include <cmath>
@@ -116,13 +122,6 @@ __device__ __forceinline__ void make_uniform(Column &c)
     c.stepy = __builtin_amdgcn_readfirstlane(c.stepy);
 }
 
-// 3D length per unit of s of the ray of detector row height zp (FP32, shared by A and A^T).
-__device__ __forceinline__ float ray_scale(double zp, double inv_lxy)
-{
-    const float mf = (float)(zp * inv_lxy);   // slope dz/ds
-    return sqrtf(fmaf(mf, mf, 1.0f));
-}
-
 // The ray of height zp on the detector (xy length lxy) is at height
 // z = zp (s + sf) / lxy; it crosses z plane k (z = k - nz/2) at
 //     s = (k - nz/2) * im - sf,   im = lxy / zp,
@@ -137,7 +136,6 @@ struct RayZ {
     double im, sf;      // see zplane_s
     float lzi, lzo;     // s-range inside the z slab of the volume
     float szn;          // next z-plane crossing
-    float scale;        // 3D length per unit s: sqrt(1 + m^2)
     int iz, zstep;
 };
 
@@ -147,7 +145,6 @@ __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, 
     const double2 zr = P.rzp[min(iv, P.nv - 1)];
     const double zp = zr.x;
     z.sf = c.sf;
-    z.scale = ray_scale(zp, c.inv_lxy);
     double lzi, lzo;
     const double z_in = zp * (c.s_in + c.sf) * c.inv_lxy;   // height where the line enters the xy box
     if (zp != 0.0) {
@@ -389,15 +386,17 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
         for (int r = 0; r < R; ++r) {
             if (iv[r] > P.iv_hi) continue;
             const int64_t idx = base + iv[r];
-            const double w = hit ? acc[r] * (MODE == PM_COUNT ? 1.0 : (double)z[r].scale) : 0.0;
+            const double sc = P.scale[(int64_t)T.iu * P.nv + iv[r]];
+            const double w = hit ? acc[r] * (MODE == PM_COUNT ? 1.0 : sc) : 0.0;
             if (MODE == PM_PLAIN || MODE == PM_COUNT) {
                 out[idx] = (float)w;
             } else if (MODE == PM_WEIGHTED) {
+                // output pre-scaled for the adjoint: sc Lambda A p
                 const double l = lam[idx];
-                out[idx] = (float)(l * w);
+                out[idx] = (float)(sc * l * w);
                 part += w * l * w;
             } else {
-                out[idx] = (float)((double)lam[idx] * ((double)y[idx] - w));
+                out[idx] = (float)(sc * (double)lam[idx] * ((double)y[idx] - w));
             }
         }
     }
@@ -435,7 +434,7 @@ __global__ __launch_bounds__(256) void k_back_scatter(const ProjParams P, const 
         const int iv = P.iv_lo + T.vc * P.rows_per_chunk + r * WAVE + lane;
         const bool valid = iv <= P.iv_hi;
         ray_setup(P, c, iv, valid, z[r]);
-        val[r] = valid ? sino[base + iv] * z[r].scale : 0.0f;
+        val[r] = valid ? sino[base + iv] : 0.0f;   // pre-scaled sinogram
         if (val[r] == 0.0f) {   // nothing to add: skip this ray's atomics
             z[r].lzi = INFINITY;
             z[r].lzo = -INFINITY;
@@ -486,9 +485,32 @@ __global__ void k_col_table(const ProjParams P, int64_t n_views, ColEntry *__res
 // expressions, and each lane finds the detector rows whose ray passes through
 // its voxel inside [a, b] and takes the piece length exactly as the forward
 // projector cuts it.  FP64 sums, one write per voxel, no atomics.
-template <int ZPL>
+//
+// FUSED: instead of writing A^T z, finish the CG update of the voxel in the
+// epilogue (q = A^T Lambda A p + p / sigma^2; x += alpha p; r -= alpha q) and
+// write the workgroup's partial sum of r^2, so that q never goes to memory.
+struct GatherUpdate {
+    float *x, *r;
+    const float *p;
+    const double *scal;      // [SC_COUNT][nf]
+    const double *consts;    // [0] = 1 / sigma^2
+    double *part;            // [nf * tiles per frame]
+};
+
+// Length of the ray of detector row ivr (table entry zr) inside z slab
+// [klo, klo + 1] and xy piece [fa, fb] of column entry E; 0 when disjoint.
+// For zp = 0 the table holds a huge finite 1/zp, so the slab holding z = 0
+// gets the whole piece and every other slab nothing, as in the forward walk.
+__device__ __forceinline__ float slab_piece(const ColEntry &E, double2 zr, double klo, float fa, float fb)
+{
+    const double im = E.lxy * zr.y;
+    const float e1 = (float)fma(klo, im, -E.sf), e2 = (float)fma(klo + 1.0, im, -E.sf);
+    return fminf(fb, fmaxf(e1, e2)) - fmaxf(fa, fminf(e1, e2));
+}
+
+template <int ZPL, bool FUSED>
 __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const float *__restrict__ sino,
-                                                     double *__restrict__ out)
+                                                     double *__restrict__ out, const GatherUpdate U)
 {
     const int nwaves = blockDim.x / WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -502,23 +524,24 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
     const int iy = (int)(local % P.ny);
     const int zc = (int)(local / P.ny);
     const int ix = xg * nwaves + wave;
-    if (ix >= P.nx) return;
-    if (P.active && !P.active[f]) return;
-    const double hz = 0.5 * P.nz;
+    if (P.active && !P.active[f]) return;   // the whole workgroup belongs to frame f
+    const bool col_ok = ix < P.nx;
     const float hzf = 0.5f * P.nz;
     int iz[ZPL];
+    double klo[ZPL];
     double acc[ZPL];
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         iz[k] = (zc * ZPL + k) * WAVE + lane;
+        klo[k] = (double)iz[k] - 0.5 * P.nz;
         acc[k] = 0.0;
     }
+    const int64_t v0 = col_ok ? P.view_offset[f] : 0, v1 = col_ok ? P.view_offset[f + 1] : 0;
     const float x0 = ix - 0.5f * P.nx, y0 = iy - 0.5f * P.ny;
     const float cu = 0.5f * (P.nu - 1), cv = 0.5f * (P.nv - 1);
     const float rs = (float)P.rs, rsd = (float)P.rsd;
     const float inv_du = (float)(1.0 / P.du), inv_dv = (float)(1.0 / P.dv);
     const float offu = (float)P.offu, offv = (float)P.offv;
-    const int64_t v0 = P.view_offset[f], v1 = P.view_offset[f + 1];
     for (int64_t v = v0; v < v1; ++v) {
         const double2 cs = P.cs[v];
         const float c = (float)cs.x, s = (float)cs.y;
@@ -574,33 +597,65 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 const int iva = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
                 int ivb = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
                 if (iz[k] >= P.nz) ivb = iva - 1;
-                const double klo = (double)iz[k] - hz, khi = (double)(iz[k] + 1) - hz;
-                for (int ivr = iva; ivr <= ivb; ++ivr) {
-                    const double2 zr = P.rzp[ivr];
-                    float enter, exit;
-                    if (zr.x != 0.0) {
-                        const double im = E.lxy * zr.y;
-                        const float e1 = (float)fma(klo, im, -E.sf), e2 = (float)fma(khi, im, -E.sf);
-                        enter = fminf(e1, e2);
-                        exit = fmaxf(e1, e2);
-                    } else {
-                        const double z_in = zr.x * (E.s_in + E.sf) * E.inv_lxy;
-                        const bool in = z_in >= -hz && z_in < hz && min(max((int)floor(z_in + hz), 0), P.nz - 1) == iz[k];
-                        enter = in ? -INFINITY : INFINITY;
-                        exit = in ? INFINITY : -INFINITY;
-                    }
-                    const float l = fminf(fb, exit) - fmaxf(fa, enter);
-                    if (l > 0.0f) vacc[k] = fmaf(l * ray_scale(zr.x, E.inv_lxy), srow[ivr], vacc[k]);
+                // the first two candidate rows without a branch (indices clamped into the table),
+                // the rare further ones in a loop
+                const int ia = min(iva, P.iv_hi), ib = min(iva + 1, P.iv_hi);
+                const double2 za = P.rzp[ia], zb = P.rzp[ib];
+                const float sva = srow[ia], svb = srow[ib];
+                const float la = slab_piece(E, za, klo[k], fa, fb);
+                const float lb = slab_piece(E, zb, klo[k], fa, fb);
+                float acc_k = vacc[k];
+                if (iva <= ivb && la > 0.0f) acc_k = fmaf(la, sva, acc_k);
+                if (iva + 1 <= ivb && lb > 0.0f) acc_k = fmaf(lb, svb, acc_k);
+                for (int ivr = iva + 2; ivr <= ivb; ++ivr) {
+                    const float l = slab_piece(E, P.rzp[ivr], klo[k], fa, fb);
+                    if (l > 0.0f) acc_k = fmaf(l, srow[ivr], acc_k);
                 }
+                vacc[k] = acc_k;
             }
         }
 #pragma unroll
         for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
     }
-    double *o = out + (int64_t)f * P.nvox + (int64_t)(iy * P.nx + ix) * P.nz;
+    const int64_t col = (int64_t)f * P.nvox + (int64_t)(iy * P.nx + (col_ok ? ix : 0)) * P.nz;
+    if (!FUSED) {
+        if (!col_ok) return;
 #pragma unroll
-    for (int k = 0; k < ZPL; ++k)
-        if (iz[k] < P.nz) o[iz[k]] = acc[k];
+        for (int k = 0; k < ZPL; ++k)
+            if (iz[k] < P.nz) out[col + iz[k]] = acc[k];
+        return;
+    }
+    const double is2 = U.consts[0];
+    const double alpha = U.scal[SC_ALPHA * P.nf + f];
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < ZPL; ++k) {
+        if (col_ok && iz[k] < P.nz) {
+            const int64_t i = col + iz[k];
+            const double pv = U.p[i];
+            const double q = acc[k] + pv * is2;
+            U.x[i] = (float)((double)U.x[i] + alpha * pv);
+            const float rf = (float)((double)U.r[i] - alpha * q);
+            U.r[i] = rf;
+            part += (double)rf * (double)rf;
+        }
+    }
+    __shared__ double red[4];
+    part = wave_sum(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < nwaves; ++w) sum += red[w];
+        U.part[t] = sum;
+    }
+}
+
+// sino[i] *= scale[i mod (nu nv)]
+__global__ void k_prescale(float *__restrict__ sino, const float *__restrict__ scale, int64_t per_view, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        sino[i] *= scale[i % per_view];
 }
 
 template <int R, bool STEEP>
@@ -638,6 +693,7 @@ ProjParams msf_plan::proj_params(bool with_active) const
     pp.rzp = d_rzp;
     pp.cols = d_cols;
     pp.g_zpl = nz > 64 ? 2 : 1;
+    pp.scale = d_scale;
     const int gw = tiles.waves_per_group;
     pp.g_tiles_per_frame = (int64_t)((nx + gw - 1) / gw) * ny * ((nz + WAVE * pp.g_zpl - 1) / (WAVE * pp.g_zpl));
     return pp;
@@ -686,8 +742,37 @@ hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_
     const int64_t total = pp.g_tiles_per_frame * P.nf;
     if (total == 0) return hipSuccess;
     const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
-    if (pp.g_zpl == 2) hipLaunchKernelGGL((k_back_gather<2>), grid, block, 0, s, pp, sino, vol_out);
-    else hipLaunchKernelGGL((k_back_gather<1>), grid, block, 0, s, pp, sino, vol_out);
+    const GatherUpdate U{};
+    if (pp.g_zpl == 2) hipLaunchKernelGGL((k_back_gather<2, false>), grid, block, 0, s, pp, sino, vol_out, U);
+    else hipLaunchKernelGGL((k_back_gather<1, false>), grid, block, 0, s, pp, sino, vol_out, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s)
+{
+    const ProjParams pp = P.proj_params(true);
+    const int64_t total = pp.g_tiles_per_frame * P.nf;
+    if (total == 0) return hipSuccess;
+    if (total > P.part_g_per_frame * P.nf) return hipErrorInvalidValue;   // partial buffer sized for other tiles
+    const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
+    GatherUpdate U;
+    U.x = P.x;
+    U.r = P.r;
+    U.p = P.p;
+    U.scal = P.scal;
+    U.consts = P.consts;
+    U.part = P.part_g;
+    if (pp.g_zpl == 2) hipLaunchKernelGGL((k_back_gather<2, true>), grid, block, 0, s, pp, P.sz, nullptr, U);
+    else hipLaunchKernelGGL((k_back_gather<1, true>), grid, block, 0, s, pp, P.sz, nullptr, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_prescale(const msf_plan &P, float *sino, hipStream_t s)
+{
+    const int64_t n = P.nmeas_total;
+    if (n == 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_prescale, dim3((unsigned)g), dim3(256), 0, s, sino, P.d_scale, (int64_t)P.nu * P.nv, n);
     return hipGetLastError();
 }
 

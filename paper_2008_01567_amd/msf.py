@@ -83,7 +83,7 @@ EXPORTS = ["msf_solve_opts_default", "msf_plan_create", "msf_plan_destroy", "msf
            "msf_plan_get_tiles", "msf_plan_sizes", "msf_project", "msf_backproject", "msf_prox_solve",
            "msf_last_error", "msf_version", "msf_plan_set_timing", "msf_plan_get_timing",
            "msf_count_intersections", "msf_prox_features", "msf_cnn_create", "msf_cnn_destroy",
-           "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step", "msf_mace_opts_default", "msf_mace_run"]
+           "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step", "msf_mace_opts_default", "msf_mace_run", "msf_plan_autotune"]
 
 
 def lib():
@@ -111,6 +111,7 @@ def lib():
         L.msf_count_intersections.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.msf_prox_features.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
         L.msf_mace_opts_default.argtypes = [C.POINTER(msf_mace_opts)]
+        L.msf_plan_autotune.argtypes = [vp, C.c_char_p, C.POINTER(msf_tiles), vp]
         L.msf_mace_run.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(msf_mace_opts), vp,
                                    C.POINTER(msf_mace_stats), vp]
         L.msf_cnn_create.argtypes = [C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_float), C.POINTER(vp)]
@@ -186,6 +187,13 @@ class Plan:
     def set_tiles(self, rays_per_lane=3, waves_per_group=4, back_mode=1, xcd_remap=1):
         t = msf_tiles(rays_per_lane, waves_per_group, back_mode, xcd_remap)
         _check(lib().msf_plan_set_tiles(self._h, C.byref(t)))
+
+    def autotune(self, cache_path=None, stream=None) -> dict:
+        """Time every launch shape on this geometry and keep the fastest (msf_plan_autotune)."""
+        t = msf_tiles()
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().msf_plan_autotune(self._h, cp, C.byref(t), _stream(stream)))
+        return {k: getattr(t, k) for k, _ in msf_tiles._fields_}
 
     def get_tiles(self) -> dict:
         t = msf_tiles()
