@@ -25,8 +25,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "prox-map voxel·views/s at 1e-4 rel err: learned+batched vs plain CG; HBM GB/s"
-PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
+# ALU peak of the projector kernels: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+# 39.3 T lane-instructions/s, i.e. 78.6 TFLOP/s of non-packed FP32 (or FP64)
+# FMA.  The published 157.3 TFLOP/s FP32 figure needs packed dual-FP32
+# instructions, which the library is built without.
+PEAK_ALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (two passes over one plain solve of the 128^3 x 16 workload,
+# launch shape 3,4,1,1), each scaled by what the same counter reads for the
+# library's plain copy kernel of known size in the same run (read x2.0, write
+# x1.0).  Valid only for the projector source they were taken on.
+MEASURED_TRAFFIC = {
+    "source_sha256": "de6059f6413c915b8525efd71649c96dc01bd1189a221aa7c6ead3a0e7097ed7",
+    "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 4, "back_mode": 1, "xcd_remap": 1},
+    "kernel": "backprojector k_back_gather", "bytes_per_launch": 696.5e6,
+    "read_bytes": 433.0e6, "write_bytes": 263.5e6, "l2_hit_rate": 0.883,
+    "profile": "profiles/gather_update_c2_128x16_counters.md",
+}
 
 
 
@@ -160,6 +177,16 @@ def main():
     nnz_total = int(nnz.sum())
     flops = 2.0 * nnz_total        # one FMA per ray-voxel intersection (SpMV convention)
     achieved = flops / (dom_ms * 1e-3) / 1e12
+    traffic = None
+    try:
+        import hashlib
+        with open(os.path.join(ROOT, "paper_2008_01567_amd", "csrc", "projector.hip"), "rb") as fh:
+            same_src = hashlib.sha256(fh.read()).hexdigest() == MEASURED_TRAFFIC["source_sha256"]
+        if same_src and MEASURED_TRAFFIC["config"] == args.config and dominant == MEASURED_TRAFFIC["kernel"] \
+                and plan.get_tiles() == MEASURED_TRAFFIC["tiles"]:
+            traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    except OSError:
+        pass
     voxel_views = geom.voxel_views()
     value = voxel_views / dt
     result = {
@@ -184,8 +211,14 @@ def main():
         "speedup_learned_vs_plain": None if net is None else dt_plain / dt,
         "kernels_ms": {"forward": fwd_ms, "back": back_ms, "timed_launches": tm["forward_launches"]},
         "nnz_A": nnz_total,
-        "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+        "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
+                     "ms_per_launch": dom_ms,
+                     "note": "2 FLOP per ray-voxel intersection (nnz of A counted by the projector); peak = "
+                             "non-packed FP32 FMA rate 256 CU x 64 lanes x 2 x 2.4 GHz; traffic = HBM bytes per "
+                             "launch from rocprofv3 FETCH_SIZE+WRITE_SIZE scaled by a copy kernel (null when the "
+                             "kernel or launch shape differs from the profiled one)",
+                     "hbm_gbs_of_traffic": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9},
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, geom, v_np, y_np, lam_np, int(st_plain["iters"][0]),
