@@ -77,6 +77,7 @@ def lib():
         L.or_prox_cg.restype = C.c_int32
         L.or_backproject_voxels.argtypes = [gp, dp, C.c_int32, dp, lp, C.c_int32, dp]
         L.or_project_rays.argtypes = [gp, dp, ip, ip, ip, C.c_int32, dp, dp]
+        L.or_voxel_columns.argtypes = [gp, dp, C.c_int32, lp, C.c_int32, ip, lp, dp, C.c_int32]
         L.or_num_threads.restype = C.c_int32
         _lib = L
     return _lib
@@ -264,6 +265,48 @@ def backproject_voxels(geom, frame, y_frame, voxels):
     lib().or_backproject_voxels(C.byref(cgeom(geom)), _p(ang, C.c_double), a1 - a0, _p(y, C.c_double),
                                 _p(vx, C.c_int64), len(vx), _p(out, C.c_double))
     return out
+
+
+def voxel_columns(geom, frame, voxels, cap=4096):
+    """Columns of one frame's A at selected voxels: [(ray indices, lengths)] with
+    frame-local ray index view*nv*nu + iv*nu + iu (slab test against every ray)."""
+    a0, a1 = int(geom.view_offset[frame]), int(geom.view_offset[frame + 1])
+    ang = np.ascontiguousarray(geom.angles[a0:a1], dtype=np.float64)
+    vx = np.ascontiguousarray(voxels, dtype=np.int64)
+    cnt = np.zeros(len(vx), dtype=np.int32)
+    ray = np.zeros(len(vx) * cap, dtype=np.int64)
+    ln = np.zeros(len(vx) * cap)
+    lib().or_voxel_columns(C.byref(cgeom(geom)), _p(ang, C.c_double), a1 - a0, _p(vx, C.c_int64), len(vx),
+                           _p(cnt, C.c_int32), _p(ray, C.c_int64), _p(ln, C.c_double), cap)
+    if (cnt > cap).any():
+        raise ValueError("voxel column longer than cap")
+    return [(ray[s * cap:s * cap + cnt[s]].copy(), ln[s * cap:s * cap + cnt[s]].copy()) for s in range(len(vx))]
+
+
+def project_ray_ids(geom, frame, rays, x_frame):
+    """Siddon projection of frame-local ray indices (view*nv*nu + iv*nu + iu)."""
+    rays = np.asarray(rays, dtype=np.int64)
+    view, rem = np.divmod(rays, geom.nu * geom.nv)
+    iv, iu = np.divmod(rem, geom.nu)
+    return project_rays(geom, frame, view, iv, iu, x_frame)
+
+
+def gradient_at_voxels(geom, frame, voxels, x, v, y, lam, sigma):
+    """Components j of the proximal objective's gradient
+    A^T Lambda (A x - y) + (x - v) / sigma^2 of one frame, and of b = A^T Lambda y + v / sigma^2,
+    at selected voxels (FP64; x, v [nvox], y, lam the frame's sinogram)."""
+    cols = voxel_columns(geom, frame, voxels)
+    rays = np.unique(np.concatenate([c[0] for c in cols])) if cols else np.zeros(0, np.int64)
+    ax = dict(zip(rays.tolist(), project_ray_ids(geom, frame, rays, x).tolist()))
+    x = np.asarray(x, dtype=np.float64).reshape(-1)
+    v = np.asarray(v, dtype=np.float64).reshape(-1)
+    grad = np.zeros(len(voxels))
+    b = np.zeros(len(voxels))
+    for s, (rr, ll) in enumerate(cols):
+        axr = np.array([ax[r] for r in rr.tolist()])
+        grad[s] = np.sum(ll * lam[rr] * (axr - y[rr])) + (x[voxels[s]] - v[voxels[s]]) / sigma ** 2
+        b[s] = np.sum(ll * lam[rr] * y[rr]) + v[voxels[s]] / sigma ** 2
+    return grad, b
 
 
 def make_measurement(cfg, geom, x0, frames=None):

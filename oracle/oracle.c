@@ -368,6 +368,40 @@ void or_backproject_voxels(const or_geom *g, const double *angles, int32_t nview
     }
 }
 
+/* Column vox of one frame's system matrix: every ray (view, iv, iu) that
+ * meets the voxel, by the voxel's own slab test, with its length.  Writes at
+ * most cap entries (ray index view*nv*nu + iv*nu + iu) and returns the count. */
+int32_t or_voxel_column(const or_geom *g, const double *angles, int32_t nviews, int64_t vox, int64_t *ray,
+                        double *len, int32_t cap)
+{
+    int32_t n = 0;
+    for (int view = 0; view < nviews; view++)
+        for (int iv = 0; iv < g->nv; iv++)
+            for (int iu = 0; iu < g->nu; iu++) {
+                double S[3], D[3];
+                or_ray(g, angles[view], iu, iv, S, D);
+                double l = or_voxel_length(g, S, D, vox);
+                if (l > 0.0) {
+                    if (n < cap) {
+                        ray[n] = ((int64_t)view * g->nv + iv) * g->nu + iu;
+                        len[n] = l;
+                    }
+                    n++;
+                }
+            }
+    return n;
+}
+
+/* or_voxel_column for nsel voxels (in parallel): entries of voxel s at
+ * ray[s*cap ..], len[s*cap ..], their count in count[s]. */
+void or_voxel_columns(const or_geom *g, const double *angles, int32_t nviews, const int64_t *vox, int32_t nsel,
+                      int32_t *count, int64_t *ray, double *len, int32_t cap)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < nsel; s++)
+        count[s] = or_voxel_column(g, angles, nviews, vox[s], ray + (int64_t)s * cap, len + (int64_t)s * cap, cap);
+}
+
 /* Projection of selected rays (view, iv, iu) of one frame by Siddon. */
 void or_project_rays(const or_geom *g, const double *angles, const int32_t *view, const int32_t *iv,
                      const int32_t *iu, int32_t nsel, const double *x, double *out)

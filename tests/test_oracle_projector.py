@@ -205,6 +205,30 @@ def test_sampled_ray_and_voxel_routines_match_csr():
     assert np.allclose(oracle.backproject_voxels(g, f, y, vox), M.AT(y)[vox], rtol=1e-12, atol=1e-12)
 
 
+def test_voxel_columns_and_sampled_gradient_match_csr():
+    """The full-size checks' routines: a voxel's column of A, and sampled components of the
+    proximal objective's gradient A^T Lambda (A x - y) + (x - v)/sigma^2, against the CSR matrix."""
+    cfg = synth.config("c1")
+    g = synth.make_geometry(cfg)
+    f = 2
+    M = oracle.FrameMatrix(g, f)
+    rng = np.random.default_rng(9)
+    vox = rng.integers(0, M.ncols, size=12)
+    cols = oracle.voxel_columns(g, f, vox)
+    for j, (rays, lens) in zip(vox, cols):
+        e = np.zeros(M.ncols)
+        e[j] = 1.0
+        col = M.A(e)
+        assert set(rays.tolist()) == set(np.nonzero(col > 1e-12)[0].tolist())
+        assert np.allclose(lens, col[rays], rtol=1e-12, atol=1e-13)
+    x, v = rng.uniform(size=M.ncols), rng.uniform(size=M.ncols)
+    y, lam = rng.uniform(size=M.nrows), rng.uniform(0.5, 2.0, size=M.nrows)
+    grad, b = oracle.gradient_at_voxels(g, f, vox, x, v, y, lam, 0.5)
+    want = M.AT(lam * (M.A(x) - y)) + (x - v) / 0.25
+    assert np.allclose(grad, want[vox], rtol=1e-12, atol=1e-12)
+    assert np.allclose(b, (M.AT(lam * y) + v / 0.25)[vox], rtol=1e-12, atol=1e-12)
+
+
 def test_rays_missing_volume_are_zero_rows():
     """A detector much wider than the volume: outer rays miss and their rows are empty."""
     g = _geom(n=(6, 6, 6), det=(40, 3), rs=30.0, rsd=60.0, angles=(0.2,))
