@@ -360,13 +360,13 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
     HIPCHK(hipEventCreate(&e1));
     auto time_it = [&](auto &&fn) -> float {
         float best = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep < 2; ++rep) {
             if (hipEventRecord(e0, s) != hipSuccess || fn() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess)
                 return 1e30f;
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0) best = std::min(best, ms);   // first run warms caches and code
+            if (rep > 0) best = std::min(best, ms);   // the first run warms caches and code
         }
         return best;
     };
@@ -375,6 +375,7 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
     float best_t = 1e30f;
     const int R[] = {1, 2, 3, 4, 6}, W[] = {1, 2, 4};
     const int need = (P->iv_hi - P->iv_lo + 64) / 64;
+    // forward + voxel-driven adjoint over every shape
     for (int xr = 0; xr <= 1; ++xr)
         for (int w : W)
             for (int r : R) {
@@ -384,14 +385,21 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
                 if (setup_tiles(*P) != MSF_OK) continue;
                 const float tf = time_it([&] { return launch_forward(*P, PM_WEIGHTED, P->p, nullptr, P->sz, false, s); });
                 const float tg = time_it([&] { return launch_back(*P, P->sz, P->bp, false, s); });
-                P->tiles.back_mode = 0;
-                const float ts = time_it([&] {
-                    hipError_t e = launch_fill_d(P->bp, P->nvox_total, s);
-                    return e != hipSuccess ? e : launch_back(*P, P->sz, P->bp, false, s);
-                });
-                if (tf + tg < best_t) { best_t = tf + tg; best = t; best.back_mode = 1; }
-                if (tf + ts < best_t) { best_t = tf + ts; best = t; best.back_mode = 0; }
+                if (tf + tg < best_t) { best_t = tf + tg; best = t; }
             }
+    // the ray-driven scatter adjoint at the best shape (it shares the forward's tiling)
+    if (best_t < 1e30f) {
+        P->tiles = best;
+        P->tiles.back_mode = 0;
+        if (setup_tiles(*P) == MSF_OK) {
+            const float tf = time_it([&] { return launch_forward(*P, PM_WEIGHTED, P->p, nullptr, P->sz, false, s); });
+            const float ts = time_it([&] {
+                hipError_t e = launch_fill_d(P->bp, P->nvox_total, s);
+                return e != hipSuccess ? e : launch_back(*P, P->sz, P->bp, false, s);
+            });
+            if (tf + ts < best_t) { best_t = tf + ts; best.back_mode = 0; }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(launch_fill_d(P->bp, P->nvox_total, s));   // the solver expects a cleared accumulator

@@ -692,7 +692,7 @@ ProjParams msf_plan::proj_params(bool with_active) const
     pp.total_tiles = total_tiles();
     pp.rzp = d_rzp;
     pp.cols = d_cols;
-    pp.g_zpl = nz > 64 ? 2 : 1;
+    pp.g_zpl = std::min(4, (nz + WAVE - 1) / WAVE);   // one wave per voxel column up to nz = 256
     pp.scale = d_scale;
     const int gw = tiles.waves_per_group;
     pp.g_tiles_per_frame = (int64_t)((nx + gw - 1) / gw) * ny * ((nz + WAVE * pp.g_zpl - 1) / (WAVE * pp.g_zpl));
@@ -743,8 +743,12 @@ hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_
     if (total == 0) return hipSuccess;
     const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
     const GatherUpdate U{};
-    if (pp.g_zpl == 2) hipLaunchKernelGGL((k_back_gather<2, false>), grid, block, 0, s, pp, sino, vol_out, U);
-    else hipLaunchKernelGGL((k_back_gather<1, false>), grid, block, 0, s, pp, sino, vol_out, U);
+    switch (pp.g_zpl) {
+    case 1: hipLaunchKernelGGL((k_back_gather<1, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
+    case 2: hipLaunchKernelGGL((k_back_gather<2, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
+    case 3: hipLaunchKernelGGL((k_back_gather<3, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
+    default: hipLaunchKernelGGL((k_back_gather<4, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
+    }
     return hipGetLastError();
 }
 
@@ -762,8 +766,12 @@ hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s)
     U.scal = P.scal;
     U.consts = P.consts;
     U.part = P.part_g;
-    if (pp.g_zpl == 2) hipLaunchKernelGGL((k_back_gather<2, true>), grid, block, 0, s, pp, P.sz, nullptr, U);
-    else hipLaunchKernelGGL((k_back_gather<1, true>), grid, block, 0, s, pp, P.sz, nullptr, U);
+    switch (pp.g_zpl) {
+    case 1: hipLaunchKernelGGL((k_back_gather<1, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
+    case 2: hipLaunchKernelGGL((k_back_gather<2, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
+    case 3: hipLaunchKernelGGL((k_back_gather<3, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
+    default: hipLaunchKernelGGL((k_back_gather<4, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
+    }
     return hipGetLastError();
 }
 

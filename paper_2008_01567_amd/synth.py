@@ -144,6 +144,9 @@ CONFIGS = {
     "c3s": Config(13, (40, 44, 36), 5, (64, 56), "arcs", 0, 0.0, *_ratio_geom(40), 5, tol=1e-6),
     "c5s": Config(15, (48, 40, 32), 4, (72, 48), "interlaced", 20, 180.0, *_ratio_geom(48), 6,
                   cylinders=2, moving=True, tol=1e-6, supersample=2),
+    # tall volumes (nz > 128): several z voxels per lane in the voxel-driven adjoint
+    "tall3": Config(16, (20, 18, 150), 2, (32, 164), "golden", 6, 180.0, 1000.0, 2000.0, 3, tol=1e-6),
+    "tall4": Config(17, (16, 14, 230), 2, (28, 244), "interlaced", 5, 360.0, 1000.0, 2000.0, 3, tol=1e-6),
 }
 
 

@@ -73,8 +73,36 @@ def _chords(S, D, shape, centre):
     return np.where(inside_inf & zin & (hi > lo), (hi - lo) * L, 0.0)
 
 
+def _radius(shape):
+    """Radius of a sphere about the centre that holds the shape."""
+    if shape.kind == "ellipsoid":
+        return float(np.max(shape.axes))
+    return float(np.hypot(shape.axes[0], shape.axes[2]))
+
+
+def _pixel_box(g, theta, centre, radius):
+    """Detector rows / columns whose rays can meet the sphere (conservative)."""
+    c, s = np.cos(theta), np.sin(theta)
+    S = np.array([g.src_iso * c, g.src_iso * s, 0.0])
+    rel = centre - S
+    depth = -(rel[0] * c + rel[1] * s)            # along the central ray
+    lat = -rel[0] * s + rel[1] * c                 # along e_u
+    if depth - radius <= 0:
+        return 0, g.nv, 0, g.nu
+    mag = g.src_det / depth
+    m2 = g.src_det / (depth - radius)
+    uc, vc = lat * mag, rel[2] * mag
+    half = radius * m2 + max(g.du, g.dv) + abs(uc) * (m2 / mag - 1.0) + abs(vc) * (m2 / mag - 1.0)
+    iu0 = int(np.floor((uc - half - g.det_off_u) / g.du + 0.5 * (g.nu - 1)))
+    iu1 = int(np.ceil((uc + half - g.det_off_u) / g.du + 0.5 * (g.nu - 1))) + 1
+    iv0 = int(np.floor((vc - half - g.det_off_v) / g.dv + 0.5 * (g.nv - 1)))
+    iv1 = int(np.ceil((vc + half - g.det_off_v) / g.dv + 0.5 * (g.nv - 1))) + 1
+    return max(iv0, 0), min(iv1, g.nv), max(iu0, 0), min(iu1, g.nu)
+
+
 def sinogram(cfg, g, frames=None, threads=None):
-    """Analytic y (float64) of the listed frames, concatenated like the library's sinograms."""
+    """Analytic y (float64) of the listed frames, concatenated like the library's sinograms.
+    Each shape is evaluated only on the detector box that its bounding sphere projects to."""
     frames = range(g.n_frames) if frames is None else list(frames)
     shapes = synth.make_shapes(cfg)
     jobs = []
@@ -86,10 +114,14 @@ def sinogram(cfg, g, frames=None, threads=None):
     def one(job):
         view, centres = job
         S, D = view_rays(g, g.angles[view])
-        acc = np.zeros(len(D))
+        D = D.reshape(g.nv, g.nu, 3)
+        acc = np.zeros((g.nv, g.nu))
         for s, c in zip(shapes, centres):
-            acc += s.mu * _chords(S, D, s, c)
-        return acc
+            v0, v1, u0, u1 = _pixel_box(g, g.angles[view], c, _radius(s))
+            if v1 > v0 and u1 > u0:
+                sub = np.ascontiguousarray(D[v0:v1, u0:u1]).reshape(-1, 3)
+                acc[v0:v1, u0:u1] += s.mu * _chords(S, sub, s, c).reshape(v1 - v0, u1 - u0)
+        return acc.reshape(-1)
 
     n = threads or min(16, os.cpu_count() or 1)
     with ThreadPoolExecutor(n) as ex:

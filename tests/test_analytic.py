@@ -45,6 +45,23 @@ def test_chords_match_point_sampling():
         assert np.allclose(So, S) and np.allclose(Do, D[r], rtol=0, atol=1e-12)
 
 
+def test_bounding_boxes_lose_nothing():
+    """Restricting each shape to its projected bounding box gives the same sinogram as
+    evaluating every ray."""
+    cfg = dataclasses.replace(synth.config("c5s"), cid=83)
+    g = synth.make_geometry(cfg)
+    shapes = synth.make_shapes(cfg)
+    got = _analytic.sinogram(cfg, g, frames=[0, 3])
+    full = []
+    for f in (0, 3):
+        for view in range(int(g.view_offset[f]), int(g.view_offset[f + 1])):
+            S, D = _analytic.view_rays(g, g.angles[view])
+            full.append(sum(s.mu * _analytic._chords(S, D, s, synth.frame_centre(s, cfg, f)) for s in shapes))
+    full = np.concatenate(full)
+    assert np.count_nonzero(full) > 0.05 * full.size
+    assert np.array_equal(got, full)
+
+
 def test_sinogram_approaches_oracle_projection_of_voxelised_phantom():
     errs = []
     for n in (16, 32):

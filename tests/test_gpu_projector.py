@@ -32,7 +32,7 @@ def _frame_rel(g, got, want):
     return max(errs)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s"])
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s", "tall4"])
 def test_project_matches_oracle(msf, name):
     cfg, g, x0, v, y, lam = problem(name)
     print("case", name, flush=True)
@@ -44,7 +44,8 @@ def test_project_matches_oracle(msf, name):
     assert np.all(got[want == 0.0] == 0.0)
 
 
-@pytest.mark.parametrize("name,back", [("c1", 1), ("c3s", 1), ("c5s", 1), ("c1", 0), ("c3s", 0)])
+@pytest.mark.parametrize("name,back", [("c1", 1), ("c3s", 1), ("c5s", 1), ("c1", 0), ("c3s", 0), ("tall3", 1),
+                                       ("tall4", 1), ("tall4", 0)])
 def test_backproject_matches_oracle(msf, name, back):
     """Both adjoints: voxel-driven gather (1, default) and ray-driven scatter (0)."""
     cfg, g, x0, v, y, lam = problem(name)
