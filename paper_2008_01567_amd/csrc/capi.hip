@@ -31,7 +31,7 @@ void free_plan_memory(msf_plan *P)
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     P->graph = nullptr;
     P->graph_valid = false;
-    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
+    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_imtab, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
                     P->sy, P->slam, P->sz, P->part_proj, P->part_vol, P->scal, P->iscal, P->consts,
                     P->flags};
     for (void *q : ptrs)
@@ -240,18 +240,24 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
         rzp[iv] = make_double2(zp, zp != 0.0 ? 1.0 / zp : 1e290);
     }
     // 3D length per unit of xy length of the ray of pixel (u, v): sqrt(1 + (zp / lxy)^2), lxy = |pixel - source|_xy
+    // z-plane crossing slope of the ray of pixel (u, v): s = (k - nz/2) lxy / zp - sf, used by every kernel
     if ((e = dalloc(&P->d_scale, (size_t)P->nu * P->nv, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->d_imtab, (size_t)P->nu * P->nv, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
     {
         std::vector<float> sc((size_t)P->nu * P->nv);
+        std::vector<double> im((size_t)P->nu * P->nv);
         for (int iu = 0; iu < P->nu; ++iu) {
             const double u = (iu - 0.5 * (P->nu - 1)) * P->du + P->offu;
             const double lxy = std::sqrt(P->rsd * P->rsd + u * u);
             for (int iv = 0; iv < P->nv; ++iv) {
                 const double m = rzp[iv].x / lxy;
                 sc[(size_t)iu * P->nv + iv] = (float)std::sqrt(1.0 + m * m);
+                im[(size_t)iu * P->nv + iv] = lxy * rzp[iv].y;
             }
         }
         if ((e = hipMemcpy(P->d_scale, sc.data(), sizeof(float) * sc.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(hip_fail(e, "hipMemcpy"));
+        if ((e = hipMemcpy(P->d_imtab, im.data(), sizeof(double) * im.size(), hipMemcpyHostToDevice)) != hipSuccess)
             return fail(hip_fail(e, "hipMemcpy"));
     }
     if ((e = hipMemcpy(P->d_rzp, rzp.data(), sizeof(double2) * P->nv, hipMemcpyHostToDevice)) != hipSuccess)

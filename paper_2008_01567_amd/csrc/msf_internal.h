@@ -42,6 +42,7 @@ struct ProjParams {
     int64_t nvox;                // voxels per frame
     int64_t total_tiles;
     const double2 *rzp;          // [nv] (height zp of detector row v, 1/zp; 1e290 when zp = 0)
+    const double *imtab;         // [nu][nv] lxy(u) / zp(v) (lxy = xy distance source -> pixel; 1e290 lxy when zp = 0)
     // voxel-driven backprojector
     const struct ColEntry *cols; // [n_views * nu] column table
     int64_t g_tiles_per_frame;
@@ -95,6 +96,7 @@ struct msf_plan {
     // device tables
     double2 *d_cs = nullptr;
     double2 *d_rzp = nullptr;             // [nv]
+    double *d_imtab = nullptr;            // [nu][nv]
     float *d_scale = nullptr;             // [nu][nv]
     double *part_g = nullptr;             // [nf * gather tiles per frame] ||r||^2 partials of the fused gather
     int64_t part_g_per_frame = 0;

@@ -139,7 +139,7 @@ struct RayZ {
     int iz, zstep;
 };
 
-__device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, int iv, bool valid, RayZ &z)
+__device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, int iu, int iv, bool valid, RayZ &z)
 {
     const double hz = 0.5 * P.nz;
     const double2 zr = P.rzp[min(iv, P.nv - 1)];
@@ -148,7 +148,7 @@ __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, 
     double lzi, lzo;
     const double z_in = zp * (c.s_in + c.sf) * c.inv_lxy;   // height where the line enters the xy box
     if (zp != 0.0) {
-        z.im = c.lxy * zr.y;
+        z.im = P.imtab[(int64_t)iu * P.nv + min(iv, P.nv - 1)];
         const double a = zplane_s(0, hz, z.im, c.sf), b = zplane_s(P.nz, hz, z.im, c.sf);
         lzi = fmin(a, b);
         lzo = fmax(a, b);
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
             iv[r] = P.iv_lo + T.vc * P.rows_per_chunk + r * WAVE + lane;
             acc[r] = 0.0;
             acc32[r] = 0.0f;
-            if (hit) ray_setup(P, c, iv[r], iv[r] <= P.iv_hi, z[r]);
+            if (hit) ray_setup(P, c, T.iu, iv[r], iv[r] <= P.iv_hi, z[r]);
         }
         if (hit) {
             const float *volf = vol + (int64_t)T.frame * P.nvox;
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(256) void k_back_scatter(const ProjParams P, const 
     for (int r = 0; r < R; ++r) {
         const int iv = P.iv_lo + T.vc * P.rows_per_chunk + r * WAVE + lane;
         const bool valid = iv <= P.iv_hi;
-        ray_setup(P, c, iv, valid, z[r]);
+        ray_setup(P, c, T.iu, iv, valid, z[r]);
         val[r] = valid ? sino[base + iv] : 0.0f;   // pre-scaled sinogram
         if (val[r] == 0.0f) {   // nothing to add: skip this ray's atomics
             z[r].lzi = INFINITY;
@@ -497,15 +497,30 @@ struct GatherUpdate {
     double *part;            // [nf * tiles per frame]
 };
 
-// Length of the ray of detector row ivr (table entry zr) inside z slab
-// [klo, klo + 1] and xy piece [fa, fb] of column entry E; 0 when disjoint.
-// For zp = 0 the table holds a huge finite 1/zp, so the slab holding z = 0
-// gets the whole piece and every other slab nothing, as in the forward walk.
-__device__ __forceinline__ float slab_piece(const ColEntry &E, double2 zr, double klo, float fa, float fb)
+// Length of the ray with crossing slope im (see zplane_s) inside z slab
+// [klo, klo + 1] and xy piece [fa, fb] of a column whose source sits at
+// s = -sf; <= 0 when disjoint.  For zp = 0 the table holds a huge finite
+// slope, so the slab holding z = 0 gets the whole piece and every other slab
+// nothing, as in the forward walk.
+__device__ __forceinline__ float slab_piece(double im, double sf, double klo, float fa, float fb)
 {
-    const double im = E.lxy * zr.y;
-    const float e1 = (float)fma(klo, im, -E.sf), e2 = (float)fma(klo + 1.0, im, -E.sf);
+    const float e1 = (float)fma(klo, im, -sf), e2 = (float)fma(klo + 1.0, im, -sf);
     return fminf(fb, fmaxf(e1, e2)) - fmaxf(fa, fminf(e1, e2));
+}
+
+// Raw buffer loads of element idx of a table row of n elements: the hardware
+// range check returns 0 for idx >= n, so candidates need no clamping.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float row_f32(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
+}
+__device__ __forceinline__ double row_f64(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
 }
 
 template <int ZPL, bool FUSED>
@@ -563,33 +578,24 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
         for (int iu = iu0; iu <= iu1; ++iu) {
             const ColEntry &E = P.cols[v * P.nu + iu];
             if (!E.hit) continue;
-            double xlo, xhi, ylo, yhi;
-            if (E.iex != 0.0) {
-                const double p0 = plane_s(ix, E.iex, E.cx), p1 = plane_s(ix + 1, E.iex, E.cx);
-                xlo = fmin(p0, p1);
-                xhi = fmax(p0, p1);
-            } else {
-                if (ix != E.ixf) continue;
-                xlo = -INFINITY;
-                xhi = INFINITY;
-            }
-            if (E.iey != 0.0) {
-                const double p0 = plane_s(iy, E.iey, E.cy), p1 = plane_s(iy + 1, E.iey, E.cy);
-                ylo = fmin(p0, p1);
-                yhi = fmax(p0, p1);
-            } else {
-                if (iy != E.iyf) continue;
-                ylo = -INFINITY;
-                yhi = INFINITY;
-            }
+            // the cell's x and y slabs along the line (a line parallel to an axis stays in one cell row)
+            const bool xok = E.iex != 0.0, yok = E.iey != 0.0;
+            if ((!xok && ix != E.ixf) || (!yok && iy != E.iyf)) continue;
+            const double px0 = plane_s(ix, E.iex, E.cx), px1 = plane_s(ix + 1, E.iex, E.cx);
+            const double py0 = plane_s(iy, E.iey, E.cy), py1 = plane_s(iy + 1, E.iey, E.cy);
+            const double xlo = xok ? fmin(px0, px1) : -INFINITY, xhi = xok ? fmax(px0, px1) : INFINITY;
+            const double ylo = yok ? fmin(py0, py1) : -INFINITY, yhi = yok ? fmax(py0, py1) : INFINITY;
             const double sa = fmax(fmax(xlo, ylo), E.s_in), sb = fmin(fmin(xhi, yhi), E.s_out);
-            const float fa = (float)sa, fb = (float)sb;
+            // canonical once here, so the per-voxel min / max below need no canonicalisation
+            const float fa = __builtin_canonicalizef((float)sa), fb = __builtin_canonicalizef((float)sb);
             if (!(fb > fa)) continue;
             // ray height z = zp (s + sf) / lxy: rows through [zlo, zhi] within [a, b]
             const float lxyf = (float)E.lxy;
             const float ka = lxyf * __builtin_amdgcn_rcpf((float)(sa + E.sf));
             const float kb = lxyf * __builtin_amdgcn_rcpf((float)(sb + E.sf));
-            const float *srow = sino + (v * P.nu + iu) * (int64_t)P.nv;
+            const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino + (v * P.nu + iu) * (int64_t)P.nv, P.nv * 4);
+            const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + (int64_t)iu * P.nv, P.nv * 8);
+            const double sf = E.sf;
 #pragma unroll
             for (int k = 0; k < ZPL; ++k) {
                 const float zlo = iz[k] - hzf, zhi = zlo + 1.0f;
@@ -597,19 +603,18 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 const int iva = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
                 int ivb = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
                 if (iz[k] >= P.nz) ivb = iva - 1;
-                // the first two candidate rows without a branch (indices clamped into the table),
+                // the first two candidate rows without a branch (reads past the row give 0),
                 // the rare further ones in a loop
-                const int ia = min(iva, P.iv_hi), ib = min(iva + 1, P.iv_hi);
-                const double2 za = P.rzp[ia], zb = P.rzp[ib];
-                const float sva = srow[ia], svb = srow[ib];
-                const float la = slab_piece(E, za, klo[k], fa, fb);
-                const float lb = slab_piece(E, zb, klo[k], fa, fb);
+                const double ima = row_f64(irow, iva), imb = row_f64(irow, iva + 1);
+                const float sva = row_f32(srow, iva), svb = row_f32(srow, iva + 1);
+                const float la = slab_piece(ima, sf, klo[k], fa, fb);
+                const float lb = slab_piece(imb, sf, klo[k], fa, fb);
                 float acc_k = vacc[k];
                 if (iva <= ivb && la > 0.0f) acc_k = fmaf(la, sva, acc_k);
                 if (iva + 1 <= ivb && lb > 0.0f) acc_k = fmaf(lb, svb, acc_k);
                 for (int ivr = iva + 2; ivr <= ivb; ++ivr) {
-                    const float l = slab_piece(E, P.rzp[ivr], klo[k], fa, fb);
-                    if (l > 0.0f) acc_k = fmaf(l, srow[ivr], acc_k);
+                    const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
+                    if (l > 0.0f) acc_k = fmaf(l, row_f32(srow, ivr), acc_k);
                 }
                 vacc[k] = acc_k;
             }
@@ -691,6 +696,7 @@ ProjParams msf_plan::proj_params(bool with_active) const
     pp.nvox = nvox;
     pp.total_tiles = total_tiles();
     pp.rzp = d_rzp;
+    pp.imtab = d_imtab;
     pp.cols = d_cols;
     pp.g_zpl = std::min(4, (nz + WAVE - 1) / WAVE);   // one wave per voxel column up to nz = 256
     pp.scale = d_scale;
