@@ -86,7 +86,10 @@ typedef struct msf_cnn msf_cnn;
 typedef struct msf_tiles {
     int32_t rays_per_lane;       /* rays of one detector column per lane: 1, 2, 3, 4 or 6 */
     int32_t waves_per_group;     /* projector workgroup size in 64-lane waves: 1, 2 or 4 */
-    int32_t back_mode;           /* 0 = ray-driven scatter (FP64 atomic adds), 1 = voxel-driven gather (default) */
+    int32_t back_mode;           /* 0 = ray-driven scatter (FP64 atomic adds), 1 = voxel-driven gather computing
+                                    each cell's line pieces on the fly, 2 = voxel-driven gather reading them from a
+                                    per (view, xy cell) table built once per plan (default; n_views * nx * ny *
+                                    (4 + 16 K) bytes, K = 2 or 3; the plan falls back to 1 if it cannot be allocated) */
     int32_t xcd_remap;           /* 1 = keep a frame's tiles on one XCD (L2 locality) */
 } msf_tiles;
 

@@ -31,7 +31,7 @@ void free_plan_memory(msf_plan *P)
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     P->graph = nullptr;
     P->graph_valid = false;
-    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_imtab, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
+    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_imtab, P->d_cell_hdr, P->d_cell_ent, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
                     P->sy, P->slam, P->sz, P->part_proj, P->part_vol, P->scal, P->iscal, P->consts,
                     P->flags};
     for (void *q : ptrs)
@@ -84,8 +84,42 @@ int default_rays_per_lane(const msf_plan &P)
     return 6;
 }
 
+// Per (view, xy cell) piece table of the table-driven voxel adjoint, built once
+// (memory: n_views * nx * ny * (4 + 16 K) bytes).  K bounds the detector
+// columns that can meet one cell: the cell's width (at most sqrt 2) magnified
+// from its nearest possible depth, in columns, plus the 1e-3 slack of the range.
+msf_status ensure_cell_table(msf_plan &P)
+{
+    if (P.d_cell_hdr) return MSF_OK;
+    const double rmax = std::sqrt(0.25 * P.nx * P.nx + 0.25 * P.ny * P.ny);
+    const double span = std::sqrt(2.0) * P.rsd / ((P.rs - rmax) * P.du) + 2e-3;
+    P.cell_k = (int)std::floor(span) + 1;
+    const int64_t n = P.n_views * (int64_t)P.nx * P.ny;
+    hipError_t e;
+    if ((e = dalloc(&P.d_cell_hdr, (size_t)std::max<int64_t>(n, 1), P.workspace_bytes)) != hipSuccess)
+        return hip_fail(e, "hipMalloc cell table");
+    if ((e = dalloc(&P.d_cell_ent, (size_t)std::max<int64_t>(n * P.cell_k, 1), P.workspace_bytes)) != hipSuccess) {
+        (void)hipFree(P.d_cell_hdr);
+        P.d_cell_hdr = nullptr;
+        return hip_fail(e, "hipMalloc cell table");
+    }
+    int32_t overflow = 0;
+    if ((e = hipMemset(P.flags + 4, 0, sizeof(int32_t))) != hipSuccess || (e = launch_cell_table(P, nullptr)) != hipSuccess ||
+        (e = hipMemcpy(&overflow, P.flags + 4, sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "cell table");
+    if (overflow) {
+        set_error("cell table: more detector columns meet a cell than the geometry bound allows");
+        return MSF_EINVAL;
+    }
+    return MSF_OK;
+}
+
 msf_status setup_tiles(msf_plan &P)
 {
+    if (P.tiles.back_mode == 2) {
+        const msf_status st = ensure_cell_table(P);
+        if (st != MSF_OK) return st;
+    }
     const int rpc = 64 * P.tiles.rays_per_lane;
     const int64_t n_ug = (P.nu + P.tiles.waves_per_group - 1) / P.tiles.waves_per_group;
     const int64_t n_vc = P.iv_hi >= P.iv_lo ? (P.iv_hi - P.iv_lo + rpc) / rpc : 0;
@@ -123,7 +157,7 @@ bool tiles_ok(const msf_tiles &t)
     return (t.rays_per_lane == 1 || t.rays_per_lane == 2 || t.rays_per_lane == 3 || t.rays_per_lane == 4 ||
             t.rays_per_lane == 6) &&
            (t.waves_per_group == 1 || t.waves_per_group == 2 || t.waves_per_group == 4) &&
-           (t.back_mode == 0 || t.back_mode == 1) && (t.xcd_remap == 0 || t.xcd_remap == 1);
+           (t.back_mode >= 0 && t.back_mode <= 2) && (t.xcd_remap == 0 || t.xcd_remap == 1);
 }
 
 #define HIPCHK(expr)                                         \
@@ -220,7 +254,7 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
     row_range(*P);
     P->tiles.rays_per_lane = default_rays_per_lane(*P);
     P->tiles.waves_per_group = 4;
-    P->tiles.back_mode = 1;
+    P->tiles.back_mode = 2;
     P->tiles.xcd_remap = 1;
 
     auto fail = [&](msf_status st) { free_plan_memory(P); delete P; return st; };
@@ -273,7 +307,7 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
     if ((e = dalloc(&P->scal, (size_t)SC_COUNT * P->nf, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
     if ((e = dalloc(&P->iscal, (size_t)IS_COUNT * P->nf, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
     if ((e = dalloc(&P->consts, 4, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
-    if ((e = dalloc(&P->flags, 4, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
+    if ((e = dalloc(&P->flags, 8, tot)) != hipSuccess) return fail(hip_fail(e, "hipMalloc"));
     P->host_stage_bytes = sizeof(double) * (SC_COUNT * P->nf + 8) + sizeof(int32_t) * (IS_COUNT * P->nf + 8);
     if ((e = hipHostMalloc(&P->host_stage, P->host_stage_bytes, hipHostMallocDefault)) != hipSuccess)
         return fail(hip_fail(e, "hipHostMalloc"));
@@ -287,10 +321,16 @@ msf_status msf_plan_create(const msf_geometry *g, msf_plan **out)
             return fail(hip_fail(e, "hipMemset"));
     if ((e = hipMemset(P->bp, 0, sizeof(double) * std::max<int64_t>(P->nvox_total, 1))) != hipSuccess)
         return fail(hip_fail(e, "hipMemset"));
-    msf_status st = setup_tiles(*P);
-    if (st != MSF_OK) return fail(st);
     if ((e = launch_col_table(*P, nullptr)) != hipSuccess) return fail(hip_fail(e, "column table"));
     if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(hip_fail(e, "hipDeviceSynchronize"));
+    msf_status st = setup_tiles(*P);   // after the column table: the cell table is built from it
+    if (st != MSF_OK && P->tiles.back_mode == 2) {
+        // no room for the cell table: the on-the-fly voxel-driven adjoint needs none
+        P->tiles.back_mode = 1;
+        set_error("");
+        st = setup_tiles(*P);
+    }
+    if (st != MSF_OK) return fail(st);
     *out = P;
     return MSF_OK;
 }
@@ -392,6 +432,10 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
                 const float tf = time_it([&] { return launch_forward(*P, PM_WEIGHTED, P->p, nullptr, P->sz, false, s); });
                 const float tg = time_it([&] { return launch_back(*P, P->sz, P->bp, false, s); });
                 if (tf + tg < best_t) { best_t = tf + tg; best = t; }
+                P->tiles.back_mode = 2;
+                if (setup_tiles(*P) != MSF_OK) continue;
+                const float tt = time_it([&] { return launch_back(*P, P->sz, P->bp, false, s); });
+                if (tf + tt < best_t) { best_t = tf + tt; best = t; best.back_mode = 2; }
             }
     // the ray-driven scatter adjoint at the best shape (it shares the forward's tiling)
     if (best_t < 1e30f) {

@@ -504,7 +504,7 @@ hipError_t launch_cg_step(msf_plan &P, hipStream_t s, hipEvent_t *ev)
 {
     hipError_t e;
     // the voxel-driven adjoint finishes the x, r update in its epilogue
-    const bool fused = P.tiles.back_mode == 1;
+    const bool fused = P.tiles.back_mode != 0;
     if (ev && (e = hipEventRecordWithFlags(ev[0], s, hipEventRecordExternal)) != hipSuccess) return e;
     if ((e = launch_forward(P, PM_WEIGHTED, P.p, nullptr, P.sz, true, s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecordWithFlags(ev[1], s, hipEventRecordExternal)) != hipSuccess) return e;

@@ -43,6 +43,9 @@ struct ProjParams {
     int64_t total_tiles;
     const double2 *rzp;          // [nv] (height zp of detector row v, 1/zp; 1e290 when zp = 0)
     const double *imtab;         // [nu][nv] lxy(u) / zp(v) (lxy = xy distance source -> pixel; 1e290 lxy when zp = 0)
+    const int32_t *cell_hdr;     // [n_views][ny * nx] first column meeting the cell (back_mode 2), or null
+    const float4 *cell_ent;      // [n_views][ny * nx][cell_k] (fa, fb, ka, kb) of columns iu0 + e
+    int cell_k;
     // voxel-driven backprojector
     const struct ColEntry *cols; // [n_views * nu] column table
     int64_t g_tiles_per_frame;
@@ -97,6 +100,9 @@ struct msf_plan {
     double2 *d_cs = nullptr;
     double2 *d_rzp = nullptr;             // [nv]
     double *d_imtab = nullptr;            // [nu][nv]
+    int32_t *d_cell_hdr = nullptr;        // [n_views][ny * nx]   (built when back_mode 2 is first used)
+    float4 *d_cell_ent = nullptr;         // [n_views][ny * nx][cell_k]
+    int cell_k = 0;
     float *d_scale = nullptr;             // [nu][nv]
     double *part_g = nullptr;             // [nf * gather tiles per frame] ||r||^2 partials of the fused gather
     int64_t part_g_per_frame = 0;
@@ -150,6 +156,8 @@ hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_
 hipError_t launch_back(const msf_plan &P, const float *sino, double *vol, bool with_active, hipStream_t s);
 // voxel-driven A^T fused with the CG update of x and r (partials of ||r||^2 in part_g)
 hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s);
+// per (view, xy cell) piece table of the voxel-driven adjoint (back_mode 2); overflow count in flags[4]
+hipError_t launch_cell_table(msf_plan &P, hipStream_t s);
 // sino[i] *= scale[i mod (nu nv)] (internal layout)
 hipError_t launch_prescale(const msf_plan &P, float *sino, hipStream_t s);
 hipError_t launch_scale_table(msf_plan &P, hipStream_t s);

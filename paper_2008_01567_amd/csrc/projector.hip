@@ -523,7 +523,125 @@ __device__ __forceinline__ double row_f64(__amdgpu_buffer_rsrc_t r, int idx)
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
 }
 
-template <int ZPL, bool FUSED>
+// Detector columns [iu0, iu1] whose xy line can meet cell (ix, iy) in view v:
+// the projections of the cell's four corners, widened by 1e-3 column.
+__device__ __forceinline__ void cell_columns(const ProjParams &P, int64_t v, int ix, int iy, int &iu0, int &iu1)
+{
+    const float x0 = ix - 0.5f * P.nx, y0 = iy - 0.5f * P.ny;
+    const float cu = 0.5f * (P.nu - 1);
+    const float rs = (float)P.rs, rsd = (float)P.rsd;
+    const float inv_du = (float)(1.0 / P.du), offu = (float)P.offu;
+    const double2 cs = P.cs[v];
+    const float c = (float)cs.x, s = (float)cs.y;
+    float ulo = INFINITY, uhi = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float X = x0 + (q & 1), Y = y0 + (q >> 1);
+        const float b = Y * c - X * s;             // along e_u
+        const float a = rs - (X * c + Y * s);      // depth from the source (> 0)
+        const float fu = (rsd * b * __builtin_amdgcn_rcpf(a) - offu) * inv_du + cu;
+        ulo = fminf(ulo, fu);
+        uhi = fmaxf(uhi, fu);
+    }
+    iu0 = max((int)ceilf(ulo - 1e-3f), 0);
+    iu1 = min((int)floorf(uhi + 1e-3f), P.nu - 1);
+}
+
+// Piece [fa, fb] of column E's xy line inside cell (ix, iy), with the forward
+// walk's crossing expressions (so the lengths match A's bit for bit), and the
+// slopes ka, kb (zp per unit z at the piece's ends) that bound the detector
+// rows through a voxel of the cell.  False when the line misses the cell.
+__device__ __forceinline__ bool cell_piece(const ColEntry &E, int ix, int iy, float &fa, float &fb, float &ka,
+                                           float &kb)
+{
+    if (!E.hit) return false;
+    // a line parallel to an axis stays in one cell row
+    const bool xok = E.iex != 0.0, yok = E.iey != 0.0;
+    if ((!xok && ix != E.ixf) || (!yok && iy != E.iyf)) return false;
+    const double px0 = plane_s(ix, E.iex, E.cx), px1 = plane_s(ix + 1, E.iex, E.cx);
+    const double py0 = plane_s(iy, E.iey, E.cy), py1 = plane_s(iy + 1, E.iey, E.cy);
+    const double xlo = xok ? fmin(px0, px1) : -INFINITY, xhi = xok ? fmax(px0, px1) : INFINITY;
+    const double ylo = yok ? fmin(py0, py1) : -INFINITY, yhi = yok ? fmax(py0, py1) : INFINITY;
+    const double sa = fmax(fmax(xlo, ylo), E.s_in), sb = fmin(fmin(xhi, yhi), E.s_out);
+    fa = (float)sa;
+    fb = (float)sb;
+    if (!(fb > fa)) return false;
+    // ray height z = zp (s + sf) / lxy
+    const float lxyf = (float)E.lxy;
+    ka = lxyf * __builtin_amdgcn_rcpf((float)(sa + E.sf));
+    kb = lxyf * __builtin_amdgcn_rcpf((float)(sb + E.sf));
+    return true;
+}
+
+// Per (view, xy cell) table of the pieces of the columns that meet the cell:
+// hdr = first column iu0, ent[e] = (fa, fb, ka, kb) of column iu0 + e
+// (fa = +inf, fb = -inf when that column misses the cell).  Built once per
+// plan from the same cell_columns / cell_piece code the on-the-fly gather runs.
+__global__ void k_cell_table(const ProjParams P, int64_t n_views, int32_t *__restrict__ hdr,
+                             float4 *__restrict__ ent, int K, int32_t *__restrict__ overflow)
+{
+    const int64_t ncell = (int64_t)P.nx * P.ny;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_views * ncell) return;
+    const int64_t v = i / ncell;
+    const int cell = (int)(i - v * ncell);
+    const int ix = cell % P.nx, iy = cell / P.nx;
+    int iu0, iu1;
+    cell_columns(P, v, ix, iy, iu0, iu1);
+    hdr[i] = iu0;
+    int used = 0;
+    for (int iu = iu0; iu <= iu1; ++iu) {
+        float fa, fb, ka, kb;
+        if (cell_piece(P.cols[v * P.nu + iu], ix, iy, fa, fb, ka, kb)) used = iu - iu0 + 1;
+    }
+    for (int e = 0; e < K; ++e) {
+        float4 o = make_float4(INFINITY, -INFINITY, 0.0f, 0.0f);
+        const int iu = iu0 + e;
+        float fa, fb, ka, kb;
+        if (iu <= iu1 && cell_piece(P.cols[v * P.nu + iu], ix, iy, fa, fb, ka, kb)) o = make_float4(fa, fb, ka, kb);
+        ent[i * K + e] = o;
+    }
+    if (used > K) atomicAdd(overflow, 1);
+}
+
+// The voxels of one lane (z = iz[k]) against column iu's piece [fa, fb]:
+// add length * pre-scaled sinogram value of every detector row whose ray
+// passes through the voxel inside the piece.
+template <int ZPL>
+__device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino, int64_t v, int iu, double sf,
+                                              float fa, float fb, float ka, float kb, const int (&iz)[ZPL],
+                                              const double (&klo)[ZPL], float (&vacc)[ZPL])
+{
+    const float hzf = 0.5f * P.nz, cv = 0.5f * (P.nv - 1);
+    const float inv_dv = (float)(1.0 / P.dv), offv = (float)P.offv;
+    const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino + (v * P.nu + iu) * (int64_t)P.nv, P.nv * 4);
+    const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + (int64_t)iu * P.nv, P.nv * 8);
+#pragma unroll
+    for (int k = 0; k < ZPL; ++k) {
+        // rows through [zlo, zhi] within [fa, fb]: zp between z * ka and z * kb
+        const float zlo = iz[k] - hzf, zhi = zlo + 1.0f;
+        const float zp_lo = fminf(zlo * ka, zlo * kb), zp_hi = fmaxf(zhi * ka, zhi * kb);
+        const int iva = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
+        int ivb = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
+        if (iz[k] >= P.nz) ivb = iva - 1;
+        // the first two candidate rows without a branch (reads past the row give 0),
+        // the rare further ones in a loop
+        const double ima = row_f64(irow, iva), imb = row_f64(irow, iva + 1);
+        const float sva = row_f32(srow, iva), svb = row_f32(srow, iva + 1);
+        const float la = slab_piece(ima, sf, klo[k], fa, fb);
+        const float lb = slab_piece(imb, sf, klo[k], fa, fb);
+        float acc_k = vacc[k];
+        if (iva <= ivb && la > 0.0f) acc_k = fmaf(la, sva, acc_k);
+        if (iva + 1 <= ivb && lb > 0.0f) acc_k = fmaf(lb, svb, acc_k);
+        for (int ivr = iva + 2; ivr <= ivb; ++ivr) {
+            const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
+            if (l > 0.0f) acc_k = fmaf(l, row_f32(srow, ivr), acc_k);
+        }
+        vacc[k] = acc_k;
+    }
+}
+
+template <int ZPL, bool FUSED, bool TABLE>
 __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const float *__restrict__ sino,
                                                      double *__restrict__ out, const GatherUpdate U)
 {
@@ -541,7 +659,6 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
     const int ix = xg * nwaves + wave;
     if (P.active && !P.active[f]) return;   // the whole workgroup belongs to frame f
     const bool col_ok = ix < P.nx;
-    const float hzf = 0.5f * P.nz;
     int iz[ZPL];
     double klo[ZPL];
     double acc[ZPL];
@@ -552,71 +669,35 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
         acc[k] = 0.0;
     }
     const int64_t v0 = col_ok ? P.view_offset[f] : 0, v1 = col_ok ? P.view_offset[f + 1] : 0;
-    const float x0 = ix - 0.5f * P.nx, y0 = iy - 0.5f * P.ny;
-    const float cu = 0.5f * (P.nu - 1), cv = 0.5f * (P.nv - 1);
-    const float rs = (float)P.rs, rsd = (float)P.rsd;
-    const float inv_du = (float)(1.0 / P.du), inv_dv = (float)(1.0 / P.dv);
-    const float offu = (float)P.offu, offv = (float)P.offv;
+    const int64_t cell = (int64_t)iy * P.nx + ix;
+    const int64_t ncell = (int64_t)P.nx * P.ny;
     for (int64_t v = v0; v < v1; ++v) {
-        const double2 cs = P.cs[v];
-        const float c = (float)cs.x, s = (float)cs.y;
-        float ulo = INFINITY, uhi = -INFINITY;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float X = x0 + (q & 1), Y = y0 + (q >> 1);
-            const float b = Y * c - X * s;             // along e_u
-            const float a = rs - (X * c + Y * s);      // depth from the source (> 0)
-            const float fu = (rsd * b * __builtin_amdgcn_rcpf(a) - offu) * inv_du + cu;
-            ulo = fminf(ulo, fu);
-            uhi = fmaxf(uhi, fu);
-        }
-        const int iu0 = __builtin_amdgcn_readfirstlane(max((int)ceilf(ulo - 1e-3f), 0));
-        const int iu1 = __builtin_amdgcn_readfirstlane(min((int)floorf(uhi + 1e-3f), P.nu - 1));
         float vacc[ZPL];
 #pragma unroll
         for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
-        for (int iu = iu0; iu <= iu1; ++iu) {
-            const ColEntry &E = P.cols[v * P.nu + iu];
-            if (!E.hit) continue;
-            // the cell's x and y slabs along the line (a line parallel to an axis stays in one cell row)
-            const bool xok = E.iex != 0.0, yok = E.iey != 0.0;
-            if ((!xok && ix != E.ixf) || (!yok && iy != E.iyf)) continue;
-            const double px0 = plane_s(ix, E.iex, E.cx), px1 = plane_s(ix + 1, E.iex, E.cx);
-            const double py0 = plane_s(iy, E.iey, E.cy), py1 = plane_s(iy + 1, E.iey, E.cy);
-            const double xlo = xok ? fmin(px0, px1) : -INFINITY, xhi = xok ? fmax(px0, px1) : INFINITY;
-            const double ylo = yok ? fmin(py0, py1) : -INFINITY, yhi = yok ? fmax(py0, py1) : INFINITY;
-            const double sa = fmax(fmax(xlo, ylo), E.s_in), sb = fmin(fmin(xhi, yhi), E.s_out);
-            // canonical once here, so the per-voxel min / max below need no canonicalisation
-            const float fa = __builtin_canonicalizef((float)sa), fb = __builtin_canonicalizef((float)sb);
-            if (!(fb > fa)) continue;
-            // ray height z = zp (s + sf) / lxy: rows through [zlo, zhi] within [a, b]
-            const float lxyf = (float)E.lxy;
-            const float ka = lxyf * __builtin_amdgcn_rcpf((float)(sa + E.sf));
-            const float kb = lxyf * __builtin_amdgcn_rcpf((float)(sb + E.sf));
-            const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino + (v * P.nu + iu) * (int64_t)P.nv, P.nv * 4);
-            const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + (int64_t)iu * P.nv, P.nv * 8);
-            const double sf = E.sf;
-#pragma unroll
-            for (int k = 0; k < ZPL; ++k) {
-                const float zlo = iz[k] - hzf, zhi = zlo + 1.0f;
-                const float zp_lo = fminf(zlo * ka, zlo * kb), zp_hi = fmaxf(zhi * ka, zhi * kb);
-                const int iva = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
-                int ivb = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
-                if (iz[k] >= P.nz) ivb = iva - 1;
-                // the first two candidate rows without a branch (reads past the row give 0),
-                // the rare further ones in a loop
-                const double ima = row_f64(irow, iva), imb = row_f64(irow, iva + 1);
-                const float sva = row_f32(srow, iva), svb = row_f32(srow, iva + 1);
-                const float la = slab_piece(ima, sf, klo[k], fa, fb);
-                const float lb = slab_piece(imb, sf, klo[k], fa, fb);
-                float acc_k = vacc[k];
-                if (iva <= ivb && la > 0.0f) acc_k = fmaf(la, sva, acc_k);
-                if (iva + 1 <= ivb && lb > 0.0f) acc_k = fmaf(lb, svb, acc_k);
-                for (int ivr = iva + 2; ivr <= ivb; ++ivr) {
-                    const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
-                    if (l > 0.0f) acc_k = fmaf(l, row_f32(srow, ivr), acc_k);
-                }
-                vacc[k] = acc_k;
+        if (TABLE) {
+            const int64_t slot = v * ncell + cell;
+            const int iu0 = P.cell_hdr[slot];
+            for (int e = 0; e < P.cell_k; ++e) {
+                const float4 pc = P.cell_ent[slot * P.cell_k + e];
+                const float fa = __builtin_canonicalizef(pc.x), fb = __builtin_canonicalizef(pc.y);
+                if (!(fb > fa)) continue;
+                const int iu = iu0 + e;
+                gather_column<ZPL>(P, sino, v, iu, P.cols[v * P.nu + iu].sf, fa, fb, pc.z, pc.w, iz, klo, vacc);
+            }
+        } else {
+            int iu0, iu1;
+            cell_columns(P, v, ix, iy, iu0, iu1);
+            iu0 = __builtin_amdgcn_readfirstlane(iu0);
+            iu1 = __builtin_amdgcn_readfirstlane(iu1);
+            for (int iu = iu0; iu <= iu1; ++iu) {
+                const ColEntry &E = P.cols[v * P.nu + iu];
+                float fa, fb, ka, kb;
+                if (!cell_piece(E, ix, iy, fa, fb, ka, kb)) continue;
+                // canonical once here, so the per-voxel min / max need no canonicalisation
+                fa = __builtin_canonicalizef(fa);
+                fb = __builtin_canonicalizef(fb);
+                gather_column<ZPL>(P, sino, v, iu, E.sf, fa, fb, ka, kb, iz, klo, vacc);
             }
         }
 #pragma unroll
@@ -697,6 +778,9 @@ ProjParams msf_plan::proj_params(bool with_active) const
     pp.total_tiles = total_tiles();
     pp.rzp = d_rzp;
     pp.imtab = d_imtab;
+    pp.cell_hdr = d_cell_hdr;
+    pp.cell_ent = d_cell_ent;
+    pp.cell_k = cell_k;
     pp.cols = d_cols;
     pp.g_zpl = std::min(4, (nz + WAVE - 1) / WAVE);   // one wave per voxel column up to nz = 256
     pp.scale = d_scale;
@@ -741,6 +825,22 @@ hipError_t launch_back_scatter(const msf_plan &P, const float *sino, double *vol
     return hipGetLastError();
 }
 
+namespace {
+
+template <bool FUSED, bool TABLE>
+void gather_dispatch(int zpl, dim3 grid, dim3 block, hipStream_t s, const ProjParams &pp, const float *sino,
+                     double *out, const GatherUpdate &U)
+{
+    switch (zpl) {
+    case 1: hipLaunchKernelGGL((k_back_gather<1, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
+    case 2: hipLaunchKernelGGL((k_back_gather<2, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
+    case 3: hipLaunchKernelGGL((k_back_gather<3, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
+    default: hipLaunchKernelGGL((k_back_gather<4, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
+    }
+}
+
+}  // namespace
+
 hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_out, bool with_active,
                               hipStream_t s)
 {
@@ -749,11 +849,11 @@ hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_
     if (total == 0) return hipSuccess;
     const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
     const GatherUpdate U{};
-    switch (pp.g_zpl) {
-    case 1: hipLaunchKernelGGL((k_back_gather<1, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
-    case 2: hipLaunchKernelGGL((k_back_gather<2, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
-    case 3: hipLaunchKernelGGL((k_back_gather<3, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
-    default: hipLaunchKernelGGL((k_back_gather<4, false>), grid, block, 0, s, pp, sino, vol_out, U); break;
+    if (P.tiles.back_mode == 2) {
+        if (!pp.cell_hdr) return hipErrorInvalidValue;   // the cell table is built by setup_tiles
+        gather_dispatch<false, true>(pp.g_zpl, grid, block, s, pp, sino, vol_out, U);
+    } else {
+        gather_dispatch<false, false>(pp.g_zpl, grid, block, s, pp, sino, vol_out, U);
     }
     return hipGetLastError();
 }
@@ -772,12 +872,22 @@ hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s)
     U.scal = P.scal;
     U.consts = P.consts;
     U.part = P.part_g;
-    switch (pp.g_zpl) {
-    case 1: hipLaunchKernelGGL((k_back_gather<1, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
-    case 2: hipLaunchKernelGGL((k_back_gather<2, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
-    case 3: hipLaunchKernelGGL((k_back_gather<3, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
-    default: hipLaunchKernelGGL((k_back_gather<4, true>), grid, block, 0, s, pp, P.sz, nullptr, U); break;
+    if (P.tiles.back_mode == 2) {
+        if (!pp.cell_hdr) return hipErrorInvalidValue;
+        gather_dispatch<true, true>(pp.g_zpl, grid, block, s, pp, P.sz, nullptr, U);
+    } else {
+        gather_dispatch<true, false>(pp.g_zpl, grid, block, s, pp, P.sz, nullptr, U);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_table(msf_plan &P, hipStream_t s)
+{
+    const ProjParams pp = P.proj_params(false);
+    const int64_t n = P.n_views * (int64_t)P.nx * P.ny;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pp, P.n_views, P.d_cell_hdr,
+                       P.d_cell_ent, P.cell_k, P.flags + 4);
     return hipGetLastError();
 }
 
@@ -792,7 +902,7 @@ hipError_t launch_prescale(const msf_plan &P, float *sino, hipStream_t s)
 
 hipError_t launch_back(const msf_plan &P, const float *sino, double *vol, bool with_active, hipStream_t s)
 {
-    if (P.tiles.back_mode == 1) return launch_back_gather(P, sino, vol, with_active, s);
+    if (P.tiles.back_mode != 0) return launch_back_gather(P, sino, vol, with_active, s);
     return launch_back_scatter(P, sino, vol, with_active, s);
 }
 

@@ -184,7 +184,7 @@ class Plan:
         except Exception:
             pass
 
-    def set_tiles(self, rays_per_lane=3, waves_per_group=4, back_mode=1, xcd_remap=1):
+    def set_tiles(self, rays_per_lane=3, waves_per_group=4, back_mode=2, xcd_remap=1):
         t = msf_tiles(rays_per_lane, waves_per_group, back_mode, xcd_remap)
         _check(lib().msf_plan_set_tiles(self._h, C.byref(t)))
 

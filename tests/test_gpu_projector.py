@@ -44,10 +44,12 @@ def test_project_matches_oracle(msf, name):
     assert np.all(got[want == 0.0] == 0.0)
 
 
-@pytest.mark.parametrize("name,back", [("c1", 1), ("c3s", 1), ("c5s", 1), ("c1", 0), ("c3s", 0), ("tall3", 1),
-                                       ("tall4", 1), ("tall4", 0)])
+@pytest.mark.parametrize("name,back", [("c1", 2), ("c3s", 2), ("c5s", 2), ("c1", 1), ("c3s", 1), ("c5s", 1), ("c1", 0),
+                                       ("c3s", 0), ("tall3", 2), ("tall3", 1), ("tall4", 2), ("tall4", 1),
+                                       ("tall4", 0)])
 def test_backproject_matches_oracle(msf, name, back):
-    """Both adjoints: voxel-driven gather (1, default) and ray-driven scatter (0)."""
+    """Every adjoint: voxel-driven gather from the cell table (2, default) or on the fly (1),
+    and the ray-driven scatter (0)."""
     cfg, g, x0, v, y, lam = problem(name)
     print("case", name, back, flush=True)
     plan = msf.Plan(g)
@@ -58,7 +60,7 @@ def test_backproject_matches_oracle(msf, name, back):
         assert rel_l2(got[f], want[f]) <= 2e-6
 
 
-@pytest.mark.parametrize("name,back", [("c1", 1), ("c2s", 1), ("c3s", 1), ("c2s", 0)])
+@pytest.mark.parametrize("name,back", [("c1", 2), ("c2s", 2), ("c3s", 2), ("c1", 1), ("c2s", 1), ("c3s", 1), ("c2s", 0)])
 def test_dot_product_adjoint(msf, name, back):
     """<A x, y> = <x, A^T y> for the FP32 kernels (products summed in FP64)."""
     cfg, g, *_ = problem(name)
@@ -77,24 +79,29 @@ def test_dot_product_adjoint(msf, name, back):
 @pytest.mark.parametrize("rpl,wpg,xcd", [(1, 1, 0), (1, 4, 1), (2, 2, 1), (3, 4, 1), (4, 4, 0), (6, 1, 1)])
 def test_tile_shapes_give_same_results(msf, rpl, wpg, xcd):
     """Launch shapes change only the mapping of work: the forward projection is
-    bit-identical; the gather adjoint is bit-identical too (fixed order per voxel)."""
+    bit-identical; both gather adjoints are bit-identical too (the same pieces, in
+    the same fixed order per voxel, from the table or computed on the fly)."""
     cfg, g, x0, v, y, lam = problem("c2s")
     plan = msf.Plan(g)
+    assert plan.get_tiles()["back_mode"] == 2
     base = plan.project(_dev(x0)).cpu().numpy()
     bbase = plan.backproject(_dev(lam * y)).cpu().numpy()
-    plan.set_tiles(rays_per_lane=rpl, waves_per_group=wpg, back_mode=1, xcd_remap=xcd)
-    assert plan.get_tiles()["rays_per_lane"] == rpl
-    got = plan.project(_dev(x0)).cpu().numpy()
-    assert np.array_equal(got, base)
-    assert np.array_equal(plan.backproject(_dev(lam * y)).cpu().numpy(), bbase)
+    for bm in (2, 1):
+        plan.set_tiles(rays_per_lane=rpl, waves_per_group=wpg, back_mode=bm, xcd_remap=xcd)
+        assert plan.get_tiles()["rays_per_lane"] == rpl
+        got = plan.project(_dev(x0)).cpu().numpy()
+        assert np.array_equal(got, base)
+        assert np.array_equal(plan.backproject(_dev(lam * y)).cpu().numpy(), bbase), bm
     plan.set_tiles(rays_per_lane=rpl, waves_per_group=wpg, back_mode=0, xcd_remap=xcd)
     sc = plan.backproject(_dev(lam * y)).cpu().numpy()
     assert rel_l2(sc, bbase) <= 1e-6
 
 
-def test_gather_is_deterministic(msf):
+@pytest.mark.parametrize("back", [2, 1])
+def test_gather_is_deterministic(msf, back):
     cfg, g, x0, v, y, lam = problem("c3s")
     plan = msf.Plan(g)
+    plan.set_tiles(back_mode=back)
     a = plan.backproject(_dev(lam * y)).cpu().numpy()
     b = plan.backproject(_dev(lam * y)).cpu().numpy()
     assert np.array_equal(a, b)

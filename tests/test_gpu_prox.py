@@ -53,6 +53,20 @@ def test_graph_equals_eager(msf):
     assert rel_l2(xa, xb) <= 1e-5
 
 
+def test_table_and_on_the_fly_gather_give_identical_solves(msf):
+    """The CG solve with the voxel-driven adjoint reading the cell table (default) and
+    computing the pieces on the fly: the same arithmetic in the same order, bit for bit."""
+    cfg, g, x0, v, y, lam = problem("c2s")
+    out = []
+    for bm in (2, 1):
+        plan = msf.Plan(g)
+        plan.set_tiles(back_mode=bm)
+        x, st = plan.prox_solve(_dev(v), _dev(y), _dev(lam), cfg.sigma, tol=1e-6, max_iter=3000)
+        out.append((x.cpu().numpy(), st["iters"]))
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
+
+
 def test_batched_equals_per_frame(msf):
     name = "c3s"
     cfg, g, x0, v, y, lam = problem(name)
