@@ -89,7 +89,7 @@ typedef struct msf_tiles {
     int32_t back_mode;           /* 0 = ray-driven scatter (FP64 atomic adds), 1 = voxel-driven gather computing
                                     each cell's line pieces on the fly, 2 = voxel-driven gather reading them from a
                                     per (view, xy cell) table built once per plan (default; n_views * nx * ny *
-                                    (4 + 16 K) bytes, K = 2 or 3; the plan falls back to 1 if it cannot be allocated) */
+                                    (4 + 32 K) bytes, K = 2 or 3; the plan falls back to 1 if it cannot be allocated) */
     int32_t xcd_remap;           /* 1 = keep a frame's tiles on one XCD (L2 locality) */
 } msf_tiles;
 

@@ -85,7 +85,7 @@ int default_rays_per_lane(const msf_plan &P)
 }
 
 // Per (view, xy cell) piece table of the table-driven voxel adjoint, built once
-// (memory: n_views * nx * ny * (4 + 16 K) bytes).  K bounds the detector
+// (memory: n_views * nx * ny * (4 + 32 K) bytes, K = 2 or 3).  K bounds the detector
 // columns that can meet one cell: the cell's width (at most sqrt 2) magnified
 // from its nearest possible depth, in columns, plus the 1e-3 slack of the range.
 msf_status ensure_cell_table(msf_plan &P)
@@ -93,7 +93,12 @@ msf_status ensure_cell_table(msf_plan &P)
     if (P.d_cell_hdr) return MSF_OK;
     const double rmax = std::sqrt(0.25 * P.nx * P.nx + 0.25 * P.ny * P.ny);
     const double span = std::sqrt(2.0) * P.rsd / ((P.rs - rmax) * P.du) + 2e-3;
-    P.cell_k = (int)std::floor(span) + 1;
+    const int k_geom = (int)std::floor(span) + 1;
+    if (k_geom > 3) {
+        set_error("cell table: more than 3 detector columns can meet a cell on this geometry");
+        return MSF_EINVAL;
+    }
+    P.cell_k = std::max(k_geom, 2);
     const int64_t n = P.n_views * (int64_t)P.nx * P.ny;
     hipError_t e;
     if ((e = dalloc(&P.d_cell_hdr, (size_t)std::max<int64_t>(n, 1), P.workspace_bytes)) != hipSuccess)

@@ -27,6 +27,15 @@ enum ProjMode : int {
 };
 
 // Everything a projector launch needs (passed by value as a kernel argument).
+// One detector column's piece of the xy line inside one xy cell (the voxel-
+// driven adjoint's table): s range [fa, fb], slopes ka, kb bounding the rows
+// through a voxel, the column's source offset sf and its index iu.
+struct CellEntry {
+    float fa, fb, ka, kb;
+    double sf;
+    int32_t iu, pad;
+};
+
 struct ProjParams {
     int nx, ny, nz, nu, nv, nf;
     double du, dv, rs, rsd, offu, offv;
@@ -43,8 +52,8 @@ struct ProjParams {
     int64_t total_tiles;
     const double2 *rzp;          // [nv] (height zp of detector row v, 1/zp; 1e290 when zp = 0)
     const double *imtab;         // [nu][nv] lxy(u) / zp(v) (lxy = xy distance source -> pixel; 1e290 lxy when zp = 0)
-    const int32_t *cell_hdr;     // [n_views][ny * nx] first column meeting the cell (back_mode 2), or null
-    const float4 *cell_ent;      // [n_views][ny * nx][cell_k] (fa, fb, ka, kb) of columns iu0 + e
+    const int32_t *cell_hdr;     // [n_views][ny * nx] number of columns meeting the cell (back_mode 2), or null
+    const struct CellEntry *cell_ent;   // [n_views][ny * nx][cell_k], the first cell_hdr[] entries valid
     int cell_k;
     // voxel-driven backprojector
     const struct ColEntry *cols; // [n_views * nu] column table
@@ -101,7 +110,7 @@ struct msf_plan {
     double2 *d_rzp = nullptr;             // [nv]
     double *d_imtab = nullptr;            // [nu][nv]
     int32_t *d_cell_hdr = nullptr;        // [n_views][ny * nx]   (built when back_mode 2 is first used)
-    float4 *d_cell_ent = nullptr;         // [n_views][ny * nx][cell_k]
+    CellEntry *d_cell_ent = nullptr;      // [n_views][ny * nx][cell_k]
     int cell_k = 0;
     float *d_scale = nullptr;             // [nu][nv]
     double *part_g = nullptr;             // [nf * gather tiles per frame] ||r||^2 partials of the fused gather

@@ -574,11 +574,11 @@ __device__ __forceinline__ bool cell_piece(const ColEntry &E, int ix, int iy, fl
 }
 
 // Per (view, xy cell) table of the pieces of the columns that meet the cell:
-// hdr = first column iu0, ent[e] = (fa, fb, ka, kb) of column iu0 + e
-// (fa = +inf, fb = -inf when that column misses the cell).  Built once per
-// plan from the same cell_columns / cell_piece code the on-the-fly gather runs.
+// hdr = their number n, ent[0..n-1] = their pieces in increasing column order.
+// Built once per plan from the same cell_columns / cell_piece code the
+// on-the-fly gather runs, so both adjoints see identical pieces.
 __global__ void k_cell_table(const ProjParams P, int64_t n_views, int32_t *__restrict__ hdr,
-                             float4 *__restrict__ ent, int K, int32_t *__restrict__ overflow)
+                             CellEntry *__restrict__ ent, int K, int32_t *__restrict__ overflow)
 {
     const int64_t ncell = (int64_t)P.nx * P.ny;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -588,25 +588,26 @@ __global__ void k_cell_table(const ProjParams P, int64_t n_views, int32_t *__res
     const int ix = cell % P.nx, iy = cell / P.nx;
     int iu0, iu1;
     cell_columns(P, v, ix, iy, iu0, iu1);
-    hdr[i] = iu0;
-    int used = 0;
+    int n = 0;
     for (int iu = iu0; iu <= iu1; ++iu) {
-        float fa, fb, ka, kb;
-        if (cell_piece(P.cols[v * P.nu + iu], ix, iy, fa, fb, ka, kb)) used = iu - iu0 + 1;
+        const ColEntry &E = P.cols[v * P.nu + iu];
+        CellEntry c;
+        if (!cell_piece(E, ix, iy, c.fa, c.fb, c.ka, c.kb)) continue;
+        c.sf = E.sf;
+        c.iu = iu;
+        c.pad = 0;
+        if (n < K) ent[i * K + n] = c;
+        ++n;
     }
-    for (int e = 0; e < K; ++e) {
-        float4 o = make_float4(INFINITY, -INFINITY, 0.0f, 0.0f);
-        const int iu = iu0 + e;
-        float fa, fb, ka, kb;
-        if (iu <= iu1 && cell_piece(P.cols[v * P.nu + iu], ix, iy, fa, fb, ka, kb)) o = make_float4(fa, fb, ka, kb);
-        ent[i * K + e] = o;
-    }
-    if (used > K) atomicAdd(overflow, 1);
+    for (int e = n; e < K; ++e) ent[i * K + e] = CellEntry{0.0f, 0.0f, 0.0f, 0.0f, 0.0, 0, 0};
+    hdr[i] = min(n, K);
+    if (n > K) atomicAdd(overflow, 1);
 }
 
 // The voxels of one lane (z = iz[k]) against column iu's piece [fa, fb]:
 // add length * pre-scaled sinogram value of every detector row whose ray
-// passes through the voxel inside the piece.
+// passes through the voxel inside the piece.  All row indices first, then all
+// loads, then the arithmetic: one wait for the whole column.
 template <int ZPL>
 __device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino, int64_t v, int iu, double sf,
                                               float fa, float fb, float ka, float kb, const int (&iz)[ZPL],
@@ -616,24 +617,35 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
     const float inv_dv = (float)(1.0 / P.dv), offv = (float)P.offv;
     const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino + (v * P.nu + iu) * (int64_t)P.nv, P.nv * 4);
     const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + (int64_t)iu * P.nv, P.nv * 8);
+    int iva[ZPL], ivb[ZPL];
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         // rows through [zlo, zhi] within [fa, fb]: zp between z * ka and z * kb
         const float zlo = iz[k] - hzf, zhi = zlo + 1.0f;
         const float zp_lo = fminf(zlo * ka, zlo * kb), zp_hi = fmaxf(zhi * ka, zhi * kb);
-        const int iva = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
-        int ivb = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
-        if (iz[k] >= P.nz) ivb = iva - 1;
-        // the first two candidate rows without a branch (reads past the row give 0),
-        // the rare further ones in a loop
-        const double ima = row_f64(irow, iva), imb = row_f64(irow, iva + 1);
-        const float sva = row_f32(srow, iva), svb = row_f32(srow, iva + 1);
-        const float la = slab_piece(ima, sf, klo[k], fa, fb);
-        const float lb = slab_piece(imb, sf, klo[k], fa, fb);
+        iva[k] = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
+        ivb[k] = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
+        if (iz[k] >= P.nz) ivb[k] = iva[k] - 1;
+    }
+    // the first two candidate rows of every voxel without a branch (reads past the row give 0)
+    double ima[ZPL], imb[ZPL];
+    float sva[ZPL], svb[ZPL];
+#pragma unroll
+    for (int k = 0; k < ZPL; ++k) {
+        ima[k] = row_f64(irow, iva[k]);
+        imb[k] = row_f64(irow, iva[k] + 1);
+        sva[k] = row_f32(srow, iva[k]);
+        svb[k] = row_f32(srow, iva[k] + 1);
+    }
+#pragma unroll
+    for (int k = 0; k < ZPL; ++k) {
+        const float la = slab_piece(ima[k], sf, klo[k], fa, fb);
+        const float lb = slab_piece(imb[k], sf, klo[k], fa, fb);
         float acc_k = vacc[k];
-        if (iva <= ivb && la > 0.0f) acc_k = fmaf(la, sva, acc_k);
-        if (iva + 1 <= ivb && lb > 0.0f) acc_k = fmaf(lb, svb, acc_k);
-        for (int ivr = iva + 2; ivr <= ivb; ++ivr) {
+        if (iva[k] <= ivb[k] && la > 0.0f) acc_k = fmaf(la, sva[k], acc_k);
+        if (iva[k] + 1 <= ivb[k] && lb > 0.0f) acc_k = fmaf(lb, svb[k], acc_k);
+        // the rare further candidates
+        for (int ivr = iva[k] + 2; ivr <= ivb[k]; ++ivr) {
             const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
             if (l > 0.0f) acc_k = fmaf(l, row_f32(srow, ivr), acc_k);
         }
@@ -641,7 +653,10 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
     }
 }
 
-template <int ZPL, bool FUSED, bool TABLE>
+// KT = 0: the pieces are computed on the fly (back_mode 1); KT = 2, 3: they
+// come from the cell table with KT slots per (view, cell) (back_mode 2), the
+// next view's entries loaded while the current view is processed.
+template <int ZPL, bool FUSED, int KT>
 __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const float *__restrict__ sino,
                                                      double *__restrict__ out, const GatherUpdate U)
 {
@@ -669,23 +684,46 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
         acc[k] = 0.0;
     }
     const int64_t v0 = col_ok ? P.view_offset[f] : 0, v1 = col_ok ? P.view_offset[f + 1] : 0;
-    const int64_t cell = (int64_t)iy * P.nx + ix;
-    const int64_t ncell = (int64_t)P.nx * P.ny;
-    for (int64_t v = v0; v < v1; ++v) {
-        float vacc[ZPL];
+    if constexpr (KT > 0) {
+        const int64_t ncell = (int64_t)P.nx * P.ny;
+        const int64_t cell = (int64_t)iy * P.nx + ix;
+        int n_next = 0;
+        CellEntry e_next[KT];
+        if (v0 < v1) {
+            const int64_t slot = v0 * ncell + cell;
+            n_next = P.cell_hdr[slot];
 #pragma unroll
-        for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
-        if (TABLE) {
-            const int64_t slot = v * ncell + cell;
-            const int iu0 = P.cell_hdr[slot];
-            for (int e = 0; e < P.cell_k; ++e) {
-                const float4 pc = P.cell_ent[slot * P.cell_k + e];
-                const float fa = __builtin_canonicalizef(pc.x), fb = __builtin_canonicalizef(pc.y);
-                if (!(fb > fa)) continue;
-                const int iu = iu0 + e;
-                gather_column<ZPL>(P, sino, v, iu, P.cols[v * P.nu + iu].sf, fa, fb, pc.z, pc.w, iz, klo, vacc);
+            for (int j = 0; j < KT; ++j) e_next[j] = P.cell_ent[slot * KT + j];
+        }
+        for (int64_t v = v0; v < v1; ++v) {
+            const int n = n_next;
+            CellEntry ec[KT];
+#pragma unroll
+            for (int j = 0; j < KT; ++j) ec[j] = e_next[j];
+            if (v + 1 < v1) {
+                const int64_t slot = (v + 1) * ncell + cell;
+                n_next = P.cell_hdr[slot];
+#pragma unroll
+                for (int j = 0; j < KT; ++j) e_next[j] = P.cell_ent[slot * KT + j];
             }
-        } else {
+            float vacc[ZPL];
+#pragma unroll
+            for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < KT; ++j) {
+                if (j >= n) break;
+                // canonical once here, so the per-voxel min / max need no canonicalisation
+                gather_column<ZPL>(P, sino, v, ec[j].iu, ec[j].sf, __builtin_canonicalizef(ec[j].fa),
+                                   __builtin_canonicalizef(ec[j].fb), ec[j].ka, ec[j].kb, iz, klo, vacc);
+            }
+#pragma unroll
+            for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
+        }
+    } else {
+        for (int64_t v = v0; v < v1; ++v) {
+            float vacc[ZPL];
+#pragma unroll
+            for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
             int iu0, iu1;
             cell_columns(P, v, ix, iy, iu0, iu1);
             iu0 = __builtin_amdgcn_readfirstlane(iu0);
@@ -694,14 +732,12 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 const ColEntry &E = P.cols[v * P.nu + iu];
                 float fa, fb, ka, kb;
                 if (!cell_piece(E, ix, iy, fa, fb, ka, kb)) continue;
-                // canonical once here, so the per-voxel min / max need no canonicalisation
-                fa = __builtin_canonicalizef(fa);
-                fb = __builtin_canonicalizef(fb);
-                gather_column<ZPL>(P, sino, v, iu, E.sf, fa, fb, ka, kb, iz, klo, vacc);
+                gather_column<ZPL>(P, sino, v, iu, E.sf, __builtin_canonicalizef(fa), __builtin_canonicalizef(fb),
+                                   ka, kb, iz, klo, vacc);
             }
-        }
 #pragma unroll
-        for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
+            for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
+        }
     }
     const int64_t col = (int64_t)f * P.nvox + (int64_t)(iy * P.nx + (col_ok ? ix : 0)) * P.nz;
     if (!FUSED) {
@@ -827,16 +863,31 @@ hipError_t launch_back_scatter(const msf_plan &P, const float *sino, double *vol
 
 namespace {
 
-template <bool FUSED, bool TABLE>
+template <bool FUSED, int KT>
 void gather_dispatch(int zpl, dim3 grid, dim3 block, hipStream_t s, const ProjParams &pp, const float *sino,
                      double *out, const GatherUpdate &U)
 {
     switch (zpl) {
-    case 1: hipLaunchKernelGGL((k_back_gather<1, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
-    case 2: hipLaunchKernelGGL((k_back_gather<2, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
-    case 3: hipLaunchKernelGGL((k_back_gather<3, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
-    default: hipLaunchKernelGGL((k_back_gather<4, FUSED, TABLE>), grid, block, 0, s, pp, sino, out, U); break;
+    case 1: hipLaunchKernelGGL((k_back_gather<1, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
+    case 2: hipLaunchKernelGGL((k_back_gather<2, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
+    case 3: hipLaunchKernelGGL((k_back_gather<3, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
+    default: hipLaunchKernelGGL((k_back_gather<4, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
     }
+}
+
+template <bool FUSED>
+hipError_t gather_launch(const msf_plan &P, const ProjParams &pp, dim3 grid, dim3 block, hipStream_t s,
+                         const float *sino, double *out, const GatherUpdate &U)
+{
+    if (P.tiles.back_mode == 2) {
+        if (!pp.cell_hdr) return hipErrorInvalidValue;   // the cell table is built by setup_tiles
+        if (pp.cell_k == 2) gather_dispatch<FUSED, 2>(pp.g_zpl, grid, block, s, pp, sino, out, U);
+        else if (pp.cell_k == 3) gather_dispatch<FUSED, 3>(pp.g_zpl, grid, block, s, pp, sino, out, U);
+        else return hipErrorInvalidValue;
+    } else {
+        gather_dispatch<FUSED, 0>(pp.g_zpl, grid, block, s, pp, sino, out, U);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -849,13 +900,7 @@ hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_
     if (total == 0) return hipSuccess;
     const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
     const GatherUpdate U{};
-    if (P.tiles.back_mode == 2) {
-        if (!pp.cell_hdr) return hipErrorInvalidValue;   // the cell table is built by setup_tiles
-        gather_dispatch<false, true>(pp.g_zpl, grid, block, s, pp, sino, vol_out, U);
-    } else {
-        gather_dispatch<false, false>(pp.g_zpl, grid, block, s, pp, sino, vol_out, U);
-    }
-    return hipGetLastError();
+    return gather_launch<false>(P, pp, grid, block, s, sino, vol_out, U);
 }
 
 hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s)
@@ -872,13 +917,7 @@ hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s)
     U.scal = P.scal;
     U.consts = P.consts;
     U.part = P.part_g;
-    if (P.tiles.back_mode == 2) {
-        if (!pp.cell_hdr) return hipErrorInvalidValue;
-        gather_dispatch<true, true>(pp.g_zpl, grid, block, s, pp, P.sz, nullptr, U);
-    } else {
-        gather_dispatch<true, false>(pp.g_zpl, grid, block, s, pp, P.sz, nullptr, U);
-    }
-    return hipGetLastError();
+    return gather_launch<true>(P, pp, grid, block, s, P.sz, nullptr, U);
 }
 
 hipError_t launch_cell_table(msf_plan &P, hipStream_t s)
