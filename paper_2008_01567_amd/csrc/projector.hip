@@ -44,6 +44,22 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int FLUSH = 16;   // cells per FP32 partial sum before it is added to the FP64 ray sum
 
+// Raw buffer loads of element idx of a row of n elements (a table row, a
+// sinogram column, a voxel column): 32-bit offsets from a scalar base, and the
+// hardware range check returns 0 for idx outside [0, n).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float row_f32(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
+}
+__device__ __forceinline__ double row_f64(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
+}
+
 // Parameter of the crossing with plane k of an axis: s = k * inv + c0, with
 // inv = 1/e (direction component) and c0 = (-half - f) * inv.  Every kernel
 // computes crossings with this one expression, so A and A^T see the same
@@ -368,10 +384,11 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
                     float p1[R], p2[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) q[r] = ray_pieces(z[r], scur, snext, P.nz);
+                    const __amdgpu_buffer_rsrc_t colr = row_rsrc(colp, P.nz * 4);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        p1[r] = colp[(uint32_t)q[r].iz];
-                        p2[r] = colp[(uint32_t)q[r].iz2];
+                        p1[r] = row_f32(colr, q[r].iz);
+                        p2[r] = row_f32(colr, q[r].iz2);
                     }
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -506,21 +523,6 @@ __device__ __forceinline__ float slab_piece(double im, double sf, double klo, fl
 {
     const float e1 = (float)fma(klo, im, -sf), e2 = (float)fma(klo + 1.0, im, -sf);
     return fminf(fb, fmaxf(e1, e2)) - fmaxf(fa, fminf(e1, e2));
-}
-
-// Raw buffer loads of element idx of a table row of n elements: the hardware
-// range check returns 0 for idx >= n, so candidates need no clamping.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
-}
-__device__ __forceinline__ float row_f32(__amdgpu_buffer_rsrc_t r, int idx)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
-}
-__device__ __forceinline__ double row_f64(__amdgpu_buffer_rsrc_t r, int idx)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
 }
 
 // Detector columns [iu0, iu1] whose xy line can meet cell (ix, iy) in view v:
