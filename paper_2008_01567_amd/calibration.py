@@ -6,7 +6,9 @@ oracle x*.  The solver stops on the recursive relative residual
 calibrated against the oracle (FP64 CG of the same frames to 1e-11) and then
 frozen.  The GPU parity tests re-check the error at these tolerances.
 
-    128^3 x 16 frames, 16 views / 360 deg : tol 3e-6 -> FP64 error 3.2e-5 (frame 0)
+    128^3 x 16 frames, 16 views / 360 deg : error of frames 0, 5, 10, 15 (tests/calibrate_tol.py)
+        tol 3e-6 -> worst 3.5e-5 (501 iterations), 5e-6 -> 5.7e-5 (475), 8e-6 -> 9.3e-5 (451),
+        1.2e-5 -> 1.4e-4 (429): the error is ~11x the tolerance; 3e-6 keeps a 2.9x margin
     limited-angle arcs (40^3 x 5 frames)  : tol 1e-7 -> GPU error 2.1e-5 (FP32 floor ~2e-5)
 """
 
