@@ -124,7 +124,7 @@ def main():
     y_clean = plan.project(torch.from_numpy(x0).to(dev)).cpu().numpy()
     eps = synth.noise_eps(cfg, geom, dtype=np.float32)
     y_np, lam_np = synth.finish_measurement(y_clean, eps, synth.frame_counts(geom), geom.n_rays_per_view,
-                                            dtype=np.float32)
+                                            dtype=np.float32, model=cfg.weights)
     v = torch.from_numpy(v_np).to(dev)
     y = torch.from_numpy(y_np).to(dev)
     lam = torch.from_numpy(lam_np).to(dev)

@@ -317,4 +317,4 @@ def make_measurement(cfg, geom, x0, frames=None):
     yc = project(geom, x0, fr)
     eps = synth.noise_eps(cfg, geom, fr)
     counts = [geom.views_of(f) for f in fr]
-    return synth.finish_measurement(yc, eps, counts, geom.n_rays_per_view)
+    return synth.finish_measurement(yc, eps, counts, geom.n_rays_per_view, model=cfg.weights)

@@ -275,11 +275,25 @@ struct ScalArgs {
     int nf, bpf;
 };
 
+// Fixed-order sum of a[lo, hi) by one workgroup: 8 independent loads in
+// flight per thread, then the tail, then the workgroup reduction.
 __device__ double frame_sum(const double *a, int64_t lo, int64_t hi)
 {
-    double s = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += a[i];
-    return block_sum(s);
+    constexpr int U = 8;
+    const int64_t step = blockDim.x;
+    double s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = 0.0;
+    int64_t i = lo + threadIdx.x;
+    for (; i + (U - 1) * step < hi; i += U * step) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] += a[i + u * step];
+    }
+    for (; i < hi; i += step) s[0] += a[i];
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += s[u];
+    return block_sum(t);
 }
 
 __device__ __forceinline__ double &S(ScalArgs &A, int slot, int f) { return A.scal[slot * A.nf + f]; }

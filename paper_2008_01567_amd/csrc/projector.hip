@@ -155,6 +155,11 @@ struct RayZ {
     int iz, zstep;
 };
 
+// OPEN: the ray's z slab index is not clamped to the volume.  Outside [0, nz)
+// it addresses no voxel (the loads of the open walk return 0 there), so the
+// walk needs no clipping of the pieces to the volume's z faces: it crosses the
+// face planes like any other plane, at the same rounded parameters.
+template <bool OPEN = false>
 __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, int iu, int iv, bool valid, RayZ &z)
 {
     const double hz = 0.5 * P.nz;
@@ -179,13 +184,15 @@ __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, 
     if (!valid || !(fmin(c.s_out, lzo) > start)) {
         z.lzi = INFINITY;
         z.lzo = -INFINITY;
-        z.iz = 0;
+        z.iz = OPEN ? -(1 << 24) : 0;   // open walk: far outside, never crossing back in
         z.szn = INFINITY;
+        if (OPEN) z.zstep = 0;
         return;
     }
     z.lzi = (float)lzi;
     z.lzo = (float)lzo;
-    if (lzi >= c.s_in) z.iz = z.zstep > 0 ? 0 : P.nz - 1;
+    if (OPEN) z.iz = (int)floor(z_in + hz);
+    else if (lzi >= c.s_in) z.iz = z.zstep > 0 ? 0 : P.nz - 1;
     else z.iz = min(max((int)floor(z_in + hz), 0), P.nz - 1);
     z.szn = z.zstep ? (float)zplane_s(z.iz + (z.zstep > 0), hz, z.im, z.sf) : INFINITY;
 }
@@ -220,6 +227,20 @@ __device__ __forceinline__ void ray_advance(RayZ &z, const Pieces &q, double hz)
     const float nxt = (float)zplane_s(q.iz2 + (z.zstep > 0), hz, z.im, z.sf);
     z.szn = q.cross ? nxt : z.szn;
     z.iz = q.iz2;
+}
+
+// Open walk (see ray_setup<true>): the pieces of the cell [scur, snext] on
+// both sides of at most one z crossing, with no clipping to the volume.
+__device__ __forceinline__ Pieces ray_pieces_open(const RayZ &z, float scur, float snext)
+{
+    Pieces q;
+    q.cross = z.szn < snext;
+    const float mid = q.cross ? fmaxf(z.szn, scur) : snext;
+    q.l1 = mid - scur;
+    q.l2 = q.cross ? snext - mid : 0.0f;
+    q.iz = z.iz;
+    q.iz2 = z.iz + (q.cross ? z.zstep : 0);
+    return q;
 }
 
 // General case (steep rays): walk every z crossing inside the cell.
@@ -350,7 +371,7 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
             iv[r] = P.iv_lo + T.vc * P.rows_per_chunk + r * WAVE + lane;
             acc[r] = 0.0;
             acc32[r] = 0.0f;
-            if (hit) ray_setup(P, c, T.iu, iv[r], iv[r] <= P.iv_hi, z[r]);
+            if (hit) ray_setup<MODE != PM_COUNT && !STEEP>(P, c, T.iu, iv[r], iv[r] <= P.iv_hi, z[r]);
         }
         if (hit) {
             const float *volf = vol + (int64_t)T.frame * P.nvox;
@@ -383,7 +404,8 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
                     Pieces q[R];
                     float p1[R], p2[R];
 #pragma unroll
-                    for (int r = 0; r < R; ++r) q[r] = ray_pieces(z[r], scur, snext, P.nz);
+                    for (int r = 0; r < R; ++r) q[r] = ray_pieces_open(z[r], scur, snext);
+                    // slabs outside [0, nz) read 0 (range-checked loads)
                     const __amdgpu_buffer_rsrc_t colr = row_rsrc(colp, P.nz * 4);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {

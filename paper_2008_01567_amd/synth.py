@@ -112,6 +112,7 @@ class Config:
     tol: float = 1e-6
     supersample: int = 4
     pitch_at_iso: float = 1.0    # detector pitch measured at the isocentre
+    weights: str = "clipped"     # noise / weight model: "clipped" or "paper" (see finish_measurement)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -144,6 +145,11 @@ CONFIGS = {
     "c3s": Config(13, (40, 44, 36), 5, (64, 56), "arcs", 0, 0.0, *_ratio_geom(40), 5, tol=1e-6),
     "c5s": Config(15, (48, 40, 32), 4, (72, 48), "interlaced", 20, 180.0, *_ratio_geom(48), 6,
                   cylinders=2, moving=True, tol=1e-6, supersample=2),
+    # the paper's own noise / weight model on the 128^3 x 16 and reduced 48^2 x 40 workloads
+    "c2p": Config(22, (128, 128, 128), 16, (192, 192), "interlaced", 16, 360.0, *_ratio_geom(128), 8, tol=1e-6,
+                  weights="paper"),
+    "c2sp": Config(32, (48, 48, 40), 6, (72, 64), "interlaced", 16, 360.0, *_ratio_geom(48), 6, tol=1e-6,
+                   weights="paper"),
     # tall volumes (nz > 128): several z voxels per lane in the voxel-driven adjoint
     "tall3": Config(16, (20, 18, 150), 2, (32, 164), "golden", 6, 180.0, 1000.0, 2000.0, 3, tol=1e-6),
     "tall4": Config(17, (16, 14, 230), 2, (28, 244), "interlaced", 5, 360.0, 1000.0, 2000.0, 3, tol=1e-6),
@@ -357,13 +363,19 @@ def noise_eps(cfg: Config, geom: Geometry, frames=None, dtype=np.float64) -> np.
 
 
 def finish_measurement(y_clean: np.ndarray, eps: np.ndarray, counts, rays_per_view: int,
-                       noise_frac: float = 0.01, dtype=np.float64):
-    """Noisy measurement and weights, frame by frame.
+                       noise_frac: float = 0.01, dtype=np.float64, model: str = "clipped"):
+    """Noisy measurement and weights, frame by frame, s = noise_frac * max(y_clean of the frame).
 
-    y = y_clean + s * eps with s = noise_frac * max(y_clean of the frame);
+    model "clipped" (the workloads' stated recipe): y = y_clean + s * eps,
     Lambda = 1 / max(y, s) (inverse of the clipped measurement).
+    model "paper" (the paper's simulation, Sec. VII): y ~ N(y_clean, Lambda^-1) with
+    inverse variance Lambda = c exp(-y_clean); the paper leaves c to be chosen,
+    here c = 1 / s^2, so a ray of zero attenuation has noise s and the noise
+    grows as exp(y_clean / 2) with attenuation (Poisson-like).
     ``counts`` are the views per frame of the concatenated arrays.
     """
+    if model not in ("clipped", "paper"):
+        raise ValueError("unknown noise model %r" % model)
     y = np.empty(y_clean.shape, dtype=dtype)
     lam = np.empty(y_clean.shape, dtype=dtype)
     o = 0
@@ -371,9 +383,15 @@ def finish_measurement(y_clean: np.ndarray, eps: np.ndarray, counts, rays_per_vi
         m = int(c) * rays_per_view
         yc = y_clean[o:o + m].astype(np.float64)
         s = noise_frac * float(yc.max()) if m else 0.0
-        yy = yc + s * eps[o:o + m].astype(np.float64)
-        y[o:o + m] = yy
-        lam[o:o + m] = 1.0 / np.maximum(yy, s) if s > 0 else 0.0
+        e = eps[o:o + m].astype(np.float64)
+        if model == "clipped":
+            yy = yc + s * e
+            y[o:o + m] = yy
+            lam[o:o + m] = 1.0 / np.maximum(yy, s) if s > 0 else 0.0
+        else:
+            w = np.exp(-yc) / (s * s) if s > 0 else np.zeros_like(yc)
+            y[o:o + m] = yc + (s * np.exp(0.5 * yc) * e if s > 0 else 0.0)
+            lam[o:o + m] = w
         o += m
     return y, lam
 

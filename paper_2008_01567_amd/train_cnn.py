@@ -56,7 +56,8 @@ def make_problem(cfg, geom, plan, seed_base, dev):
     v = synth.make_v(c, x0.astype(np.float64)).astype(np.float32)
     yc = plan.project(torch.from_numpy(x0).to(dev)).cpu().numpy()
     eps = synth.noise_eps(c, geom, dtype=np.float32)
-    y, lam = synth.finish_measurement(yc, eps, synth.frame_counts(geom), geom.n_rays_per_view, dtype=np.float32)
+    y, lam = synth.finish_measurement(yc, eps, synth.frame_counts(geom), geom.n_rays_per_view, dtype=np.float32,
+                                      model=c.weights)
     return torch.from_numpy(v).to(dev), torch.from_numpy(y).to(dev), torch.from_numpy(lam).to(dev)
 
 

@@ -32,7 +32,8 @@ def _inputs(name):
     x0 = synth.make_phantom(cfg, dtype=np.float32)
     yc = _analytic.sinogram(cfg, g)
     eps = synth.noise_eps(cfg, g, dtype=np.float32)
-    y, lam = synth.finish_measurement(yc, eps, synth.frame_counts(g), g.n_rays_per_view, dtype=np.float32)
+    y, lam = synth.finish_measurement(yc, eps, synth.frame_counts(g), g.n_rays_per_view, dtype=np.float32,
+                                       model=cfg.weights)
     v = synth.make_v(cfg, x0).astype(np.float32)
     return cfg, g, x0, v, y, lam
 

@@ -44,6 +44,19 @@ def test_prox_matches_oracle(msf, name, tol):
     assert max(errs) <= 1e-4
 
 
+def test_paper_weight_model_reaches_the_fp32_floor(msf):
+    """The paper's weights Lambda = exp(-A x0) / s^2 make the system far stiffer (about 8x
+    the iterations); at the frozen rule the error reaches the FP32 floor of such systems,
+    2-4e-4 against the FP64 oracle (tighter tolerances do not lower it), not 1e-4."""
+    from paper_2008_01567_amd.calibration import FROZEN_TOL
+    cfg, g, x, st = _solve(msf, "c2sp", tol=FROZEN_TOL["c2sp"], max_iter=20000)
+    xs, _ = oracle_solution("c2sp", tol=1e-11)
+    errs = [rel_l2(x[f], xs[f]) for f in range(g.n_frames)]
+    print("c2sp iters", st["iters"].tolist(), "err", errs, flush=True)
+    assert st["status"] == msf.MSF_OK
+    assert max(errs) <= 5e-4
+
+
 def test_graph_equals_eager(msf):
     """The same 300 CG steps replayed from captured graphs and launched eagerly
     (results differ only by the order of the FP64 atomic adds)."""

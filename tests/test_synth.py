@@ -53,3 +53,9 @@ def test_measurement_recipe():
     assert np.allclose(y[:12], yc[:12] + s0 * eps[:12])
     assert np.allclose(lam[:12], 1 / np.maximum(y[:12], s0))
     assert (lam > 0).all() and np.isfinite(lam).all()
+    # the paper's model: inverse variance c exp(-y_clean) with c = 1 / s^2
+    yp, lp = synth.finish_measurement(yc, eps, [1, 1], 12, model="paper")
+    assert np.allclose(lp[:12], np.exp(-yc[:12]) / s0 ** 2)
+    assert np.allclose(yp[:12], yc[:12] + eps[:12] / np.sqrt(lp[:12]))
+    # noise of a zero-attenuation ray is s; it grows with attenuation
+    assert np.isclose(1 / np.sqrt(np.exp(-0.0) / s0 ** 2), s0)
