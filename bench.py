@@ -38,10 +38,10 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "de6059f6413c915b8525efd71649c96dc01bd1189a221aa7c6ead3a0e7097ed7",
-    "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 4, "back_mode": 1, "xcd_remap": 1},
-    "kernel": "backprojector k_back_gather", "bytes_per_launch": 696.5e6,
-    "read_bytes": 433.0e6, "write_bytes": 263.5e6, "l2_hit_rate": 0.883,
+    "source_sha256": "cf8d3be72f3a014db5980e47702e916312d420f0528e705120a809d22d09db06",
+    "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
+    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1251.8e6,
+    "read_bytes": 986.9e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.933,
     "profile": "profiles/gather_update_c2_128x16_counters.md",
 }
 
@@ -171,8 +171,8 @@ def main():
         dt, st, tm = dt_plain, st_plain, tm_plain
     fwd_ms = tm["forward_ms"] / max(tm["forward_launches"], 1)
     back_ms = tm["back_ms"] / max(tm["back_launches"], 1)
-    back_name = "backprojector k_back_gather" if plan.get_tiles()["back_mode"] == 1 else \
-        "backprojector k_back_scatter"
+    back_name = {0: "backprojector k_back_scatter", 1: "backprojector k_back_gather (on the fly)",
+                 2: "backprojector k_back_gather (cell table)"}[plan.get_tiles()["back_mode"]]
     dominant, dom_ms = ("forward projector k_forward", fwd_ms) if fwd_ms >= back_ms else (back_name, back_ms)
     nnz_total = int(nnz.sum())
     flops = 2.0 * nnz_total        # one FMA per ray-voxel intersection (SpMV convention)
