@@ -637,21 +637,27 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
                                               float fa, float fb, float ka, float kb, const int (&iz)[ZPL],
                                               const double (&klo)[ZPL], float (&vacc)[ZPL])
 {
-    const float hzf = 0.5f * P.nz, cv = 0.5f * (P.nv - 1);
-    const float inv_dv = (float)(1.0 / P.dv), offv = (float)P.offv;
+    const float hzf = 0.5f * P.nz;
+    // detector row coordinate of height zp: zp * inv_dv + (cv - offv * inv_dv), widened by 1e-3 row
+    const float inv_dv = (float)(1.0 / P.dv);
+    const float c0 = (float)(0.5 * (P.nv - 1) - P.offv / P.dv);
+    const float c_lo = c0 - 1e-3f, c_hi = c0 + 1e-3f;
     const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino + (v * P.nu + iu) * (int64_t)P.nv, P.nv * 4);
     const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + (int64_t)iu * P.nv, P.nv * 8);
     int iva[ZPL], ivb[ZPL];
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         // rows through [zlo, zhi] within [fa, fb]: zp between z * ka and z * kb
-        const float zlo = iz[k] - hzf, zhi = zlo + 1.0f;
-        const float zp_lo = fminf(zlo * ka, zlo * kb), zp_hi = fmaxf(zhi * ka, zhi * kb);
-        iva[k] = max((int)ceilf((zp_lo - offv) * inv_dv + cv - 1e-3f), P.iv_lo);
-        ivb[k] = min((int)floorf((zp_hi - offv) * inv_dv + cv + 1e-3f), P.iv_hi);
-        if (iz[k] >= P.nz) ivb[k] = iva[k] - 1;
+        const float zlo = iz[k] - hzf;
+        const float a0 = zlo * ka, b0 = zlo * kb;
+        const float zp_lo = fminf(a0, b0), zp_hi = fmaxf(a0 + ka, b0 + kb);
+        iva[k] = max((int)ceilf(fmaf(zp_lo, inv_dv, c_lo)), P.iv_lo);
+        ivb[k] = min((int)floorf(fmaf(zp_hi, inv_dv, c_hi)), P.iv_hi);
     }
-    // the first two candidate rows of every voxel without a branch (reads past the row give 0)
+    // the first two candidate rows of every voxel without a branch.  Reads past a
+    // row give 0, and a row outside [iva, ivb] misses the voxel inside the piece, so
+    // its length is <= 0 and adds nothing once clamped at 0.  (Lanes past nz are
+    // never written back.)
     double ima[ZPL], imb[ZPL];
     float sva[ZPL], svb[ZPL];
 #pragma unroll
@@ -663,11 +669,9 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
     }
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
-        const float la = slab_piece(ima[k], sf, klo[k], fa, fb);
-        const float lb = slab_piece(imb[k], sf, klo[k], fa, fb);
-        float acc_k = vacc[k];
-        if (iva[k] <= ivb[k] && la > 0.0f) acc_k = fmaf(la, sva[k], acc_k);
-        if (iva[k] + 1 <= ivb[k] && lb > 0.0f) acc_k = fmaf(lb, svb[k], acc_k);
+        const float la = fmaxf(slab_piece(ima[k], sf, klo[k], fa, fb), 0.0f);
+        const float lb = fmaxf(slab_piece(imb[k], sf, klo[k], fa, fb), 0.0f);
+        float acc_k = fmaf(lb, svb[k], fmaf(la, sva[k], vacc[k]));
         // the rare further candidates
         for (int ivr = iva[k] + 2; ivr <= ivb[k]; ++ivr) {
             const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
