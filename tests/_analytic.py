@@ -100,6 +100,34 @@ def _pixel_box(g, theta, centre, radius):
     return max(iv0, 0), min(iv1, g.nv), max(iu0, 0), min(iu1, g.nu)
 
 
+def fixture_tubes(cfg, n_tubes=2, radius=1.5, mu=0.05):
+    """Vertical tubes just outside the volume (inside the detector's field of
+    view), the fixtures of the paper's Appendix A: static cylinders parallel to
+    the rotation axis, placed on the y axis beyond the volume's face."""
+    nx, ny, nz = cfg.n
+    out = []
+    for k in range(n_tubes):
+        side = 1.0 if k % 2 == 0 else -1.0
+        centre = np.array([0.0, side * (0.5 * ny + 2.0 * radius + 1.0 + 2.0 * (k // 2)), 0.0])
+        out.append(synth.Shape("cylinder", centre, np.array([radius, radius, 2.0 * nz]), np.eye(3), mu,
+                               np.zeros(3)))
+    return out
+
+
+def shapes_sinogram(g, shapes, frames=None):
+    """Analytic sinogram of fixed shapes (no motion) for the listed frames."""
+    frames = range(g.n_frames) if frames is None else list(frames)
+    parts = []
+    for f in frames:
+        for view in range(int(g.view_offset[f]), int(g.view_offset[f + 1])):
+            S, D = view_rays(g, g.angles[view])
+            acc = np.zeros(len(D))
+            for s in shapes:
+                acc += s.mu * _chords(S, D, s, s.centre)
+            parts.append(acc)
+    return np.concatenate(parts) if parts else np.zeros(0)
+
+
 def sinogram(cfg, g, frames=None, threads=None):
     """Analytic y (float64) of the listed frames, concatenated like the library's sinograms.
     Each shape is evaluated only on the detector box that its bounding sphere projects to."""
