@@ -263,6 +263,26 @@ typedef struct msf_timing {
 msf_status msf_plan_set_timing(msf_plan *plan, int32_t enable);
 msf_status msf_plan_get_timing(const msf_plan *plan, msf_timing *out);
 
+/* Blind fixture correction of every frame's sinogram (paper Appendix A,
+ * algorithm "Blind fixture correction"), given a reconstruction x (device
+ * [n_frames][nz][ny][nx], e.g. from msf_prox_solve or msf_mace_run):
+ *   x_m    = x with the voxels farther than mask_radius (voxel units) from the
+ *            rotation axis set to 0 (a cylinder slightly smaller than the field
+ *            of view keeps the object and drops the edge artefacts);
+ *   e      = y - A x_m (mostly the projection of fixtures outside the volume);
+ *   p      = e blurred within each view by a separable Gaussian of std blur_std
+ *            detector pixels over u and v (2 ceil(3 std) + 1 normalised taps,
+ *            zero outside the detector);
+ *   c_n    = <e, p> / <p, p> over frame n's sinogram (the least-squares fit;
+ *            0 when p vanishes);
+ *   y_corr = y - c_n p.
+ * y, y_corr: device sinograms (public layout; may be the same buffer).
+ * c_out: host [n_frames], may be NULL.  EINVAL for mask_radius <= 0 or
+ * blur_std outside (0, 21.3].  Uses the plan's internal buffers and allocates
+ * a temporary sinogram; synchronises the stream. */
+msf_status msf_fixture_correct(msf_plan *plan, const float *x, const float *y, double mask_radius, double blur_std,
+                               float *y_corr, double *c_out, void *stream);
+
 /* Number of ray-voxel pieces of positive length (the nonzeros of A_n) per
  * frame, counted by the forward projector's own traversal.  per_frame: host
  * [n_frames].  Synchronises the stream. */

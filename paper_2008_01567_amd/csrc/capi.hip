@@ -171,6 +171,8 @@ bool tiles_ok(const msf_tiles &t)
         if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
     } while (0)
 
+}  // namespace
+
 // internal volume [f][ny][nx][nz] <-> public [f][nz][ny][nx]
 hipError_t vol_to_internal(const msf_plan &P, const float *in, float *out, int check, int32_t *flag, hipStream_t s)
 {
@@ -189,8 +191,6 @@ hipError_t sino_to_public(const msf_plan &P, const float *in, float *out, hipStr
 {
     return launch_transpose(in, out, P.n_views, P.nu, P.nv, 0, nullptr, s);
 }
-
-}  // namespace
 
 void set_error(const std::string &msg) { g_err = msg; }
 

@@ -152,6 +152,11 @@ struct msf_plan {
 // error reporting (thread-local message)
 void set_error(const std::string &msg);
 msf_status hip_fail(hipError_t e, const char *where);
+// public <-> internal layouts (tiled transposes); check 1: count non-finite, 2: negative or non-finite, into *flag
+hipError_t vol_to_internal(const msf_plan &P, const float *in, float *out, int check, int32_t *flag, hipStream_t s);
+hipError_t vol_to_public(const msf_plan &P, const float *in, float *out, hipStream_t s);
+hipError_t sino_to_internal(const msf_plan &P, const float *in, float *out, int check, int32_t *flag, hipStream_t s);
+hipError_t sino_to_public(const msf_plan &P, const float *in, float *out, hipStream_t s);
 
 // ------------------------------------------------------------ launchers --
 hipError_t launch_forward(const msf_plan &P, int mode, const float *vol, const float *y, float *out,

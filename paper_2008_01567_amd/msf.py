@@ -83,7 +83,8 @@ EXPORTS = ["msf_solve_opts_default", "msf_plan_create", "msf_plan_destroy", "msf
            "msf_plan_get_tiles", "msf_plan_sizes", "msf_project", "msf_backproject", "msf_prox_solve",
            "msf_last_error", "msf_version", "msf_plan_set_timing", "msf_plan_get_timing",
            "msf_count_intersections", "msf_prox_features", "msf_cnn_create", "msf_cnn_destroy",
-           "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step", "msf_mace_opts_default", "msf_mace_run", "msf_plan_autotune"]
+           "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step", "msf_mace_opts_default", "msf_mace_run", "msf_plan_autotune",
+           "msf_fixture_correct"]
 
 
 def lib():
@@ -109,6 +110,7 @@ def lib():
         L.msf_plan_set_timing.argtypes = [vp, C.c_int32]
         L.msf_plan_get_timing.argtypes = [vp, C.POINTER(msf_timing)]
         L.msf_count_intersections.argtypes = [vp, C.POINTER(C.c_int64), vp]
+        L.msf_fixture_correct.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, C.POINTER(C.c_double), vp]
         L.msf_prox_features.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
         L.msf_mace_opts_default.argtypes = [C.POINTER(msf_mace_opts)]
         L.msf_plan_autotune.argtypes = [vp, C.c_char_p, C.POINTER(msf_tiles), vp]
@@ -212,6 +214,17 @@ class Plan:
         t = msf_timing()
         _check(lib().msf_plan_get_timing(self._h, C.byref(t)))
         return {k: getattr(t, k) for k, _ in msf_timing._fields_}
+
+    def fixture_correct(self, x, y, mask_radius, blur_std, out=None, stream=None):
+        """Blind fixture correction (msf_fixture_correct); returns (y_corr, c per frame)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_meas, dtype=torch.float32, device=y.device)
+        c = np.zeros(self.geom.n_frames)
+        _check(lib().msf_fixture_correct(self._h, _ptr(x, self.n_vox), _ptr(y, self.n_meas), float(mask_radius),
+                                         float(blur_std), _ptr(out, self.n_meas),
+                                         c.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+        return out, c
 
     def count_intersections(self, stream=None) -> np.ndarray:
         out = np.zeros(self.geom.n_frames, dtype=np.int64)
