@@ -2,6 +2,7 @@
 frame over 180 degrees) on a held-out seed: what it gains over starting from v,
 and that the learned start still leads to the oracle's answer."""
 import dataclasses
+import json
 
 import numpy as np
 import pytest
@@ -55,3 +56,20 @@ def test_trained_network_gain_on_held_out_seed(msf):
     xs = xs.reshape(v[0].shape)
     assert rel_l2(xl.cpu().numpy()[0], xs) <= 1e-4
     assert rel_l2(xp.cpu().numpy()[0], xs) <= 1e-4
+
+
+def test_training_pipeline_end_to_end(msf, tmp_path):
+    """The training driver on a small workload: triples from the plain solver,
+    library forward/backward/Adam on crops, held-out evaluation, saved network."""
+    from paper_2008_01567_amd import train_cnn
+    out = str(tmp_path / "ws_c1.npz")
+    train_cnn.main(["--config", "c1", "--problems", "3", "--eval", "1", "--steps", "60", "--batch", "2",
+                    "--crop", "16", "--lr", "3e-3", "--out", out])
+    z = np.load(out, allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    assert z["params"].shape == (train_cnn.N_PARAMS,) and np.isfinite(z["params"]).all()
+    assert meta["frames"] == 12 and meta["steps"] == 60
+    # the trained start beats v on the training distribution's held-out problem
+    ev = meta["eval"][0]
+    assert ev["start_residual_learned"] < ev["start_residual_plain"]
+    assert meta["final_loss"] < meta["loss_of_v"]
