@@ -31,7 +31,7 @@ void free_plan_memory(msf_plan *P)
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     P->graph = nullptr;
     P->graph_valid = false;
-    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_imtab, P->d_cell_hdr, P->d_cell_ent, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
+    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_imtab, P->d_cell_hdr, P->d_cell_ent, P->d_walk_head, P->d_walk_ent, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
                     P->sy, P->slam, P->sz, P->part_proj, P->part_vol, P->scal, P->iscal, P->consts,
                     P->flags};
     for (void *q : ptrs)
@@ -108,6 +108,19 @@ msf_status ensure_cell_table(msf_plan &P)
         P.d_cell_hdr = nullptr;
         return hip_fail(e, "hipMalloc cell table");
     }
+    // the forward projector's column walks: (n_views * nu) * (8 + 8 (nx + ny + 2)) bytes
+    const int64_t ncol = P.n_views * (int64_t)P.nu;
+    if ((e = dalloc(&P.d_walk_head, (size_t)std::max<int64_t>(ncol, 1), P.workspace_bytes)) != hipSuccess ||
+        (e = dalloc(&P.d_walk_ent, (size_t)std::max<int64_t>(ncol * (P.nx + P.ny + 2), 1), P.workspace_bytes)) != hipSuccess) {
+        for (void *q : {(void *)P.d_cell_hdr, (void *)P.d_cell_ent, (void *)P.d_walk_head, (void *)P.d_walk_ent})
+            if (q) (void)hipFree(q);
+        P.d_cell_hdr = nullptr;
+        P.d_cell_ent = nullptr;
+        P.d_walk_head = nullptr;
+        P.d_walk_ent = nullptr;
+        return hip_fail(e, "hipMalloc walk table");
+    }
+    if ((e = launch_walk_table(P, nullptr)) != hipSuccess) return hip_fail(e, "walk table");
     int32_t overflow = 0;
     if ((e = hipMemset(P.flags + 4, 0, sizeof(int32_t))) != hipSuccess || (e = launch_cell_table(P, nullptr)) != hipSuccess ||
         (e = hipMemcpy(&overflow, P.flags + 4, sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)

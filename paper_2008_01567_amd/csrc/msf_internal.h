@@ -36,6 +36,18 @@ struct CellEntry {
     int32_t iu, pad;
 };
 
+// The forward walk of one detector column's xy line, precomputed (back_mode
+// 2): the cells it visits in order, as (iy * nx + ix, parameter where the
+// line leaves the cell), after a head (number of cells, entry parameter).
+struct WalkEntry {
+    int32_t cell;
+    float snext;
+};
+struct WalkHead {
+    int32_t n;
+    float s_in;
+};
+
 struct ProjParams {
     int nx, ny, nz, nu, nv, nf;
     double du, dv, rs, rsd, offu, offv;
@@ -55,6 +67,9 @@ struct ProjParams {
     const int32_t *cell_hdr;     // [n_views][ny * nx] number of columns meeting the cell (back_mode 2), or null
     const struct CellEntry *cell_ent;   // [n_views][ny * nx][cell_k], the first cell_hdr[] entries valid
     int cell_k;
+    const struct WalkHead *walk_head;   // [n_views * nu] (back_mode 2), or null
+    const struct WalkEntry *walk_ent;   // [n_views * nu][walk_stride]
+    int walk_stride;                    // nx + ny + 2 (the walk's bound)
     // voxel-driven backprojector
     const struct ColEntry *cols; // [n_views * nu] column table
     int64_t g_tiles_per_frame;
@@ -111,6 +126,8 @@ struct msf_plan {
     double *d_imtab = nullptr;            // [nu][nv]
     int32_t *d_cell_hdr = nullptr;        // [n_views][ny * nx]   (built when back_mode 2 is first used)
     CellEntry *d_cell_ent = nullptr;      // [n_views][ny * nx][cell_k]
+    WalkHead *d_walk_head = nullptr;      // [n_views * nu]               (built with the cell table)
+    WalkEntry *d_walk_ent = nullptr;      // [n_views * nu][nx + ny + 2]
     int cell_k = 0;
     float *d_scale = nullptr;             // [nu][nv]
     double *part_g = nullptr;             // [nf * gather tiles per frame] ||r||^2 partials of the fused gather
@@ -172,6 +189,8 @@ hipError_t launch_back(const msf_plan &P, const float *sino, double *vol, bool w
 hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s);
 // per (view, xy cell) piece table of the voxel-driven adjoint (back_mode 2); overflow count in flags[4]
 hipError_t launch_cell_table(msf_plan &P, hipStream_t s);
+// per detector column walk table of the forward projector (back_mode 2)
+hipError_t launch_walk_table(msf_plan &P, hipStream_t s);
 // sino[i] *= scale[i mod (nu nv)] (internal layout)
 hipError_t launch_prescale(const msf_plan &P, float *sino, hipStream_t s);
 hipError_t launch_scale_table(msf_plan &P, hipStream_t s);

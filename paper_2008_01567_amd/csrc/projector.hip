@@ -347,7 +347,65 @@ __device__ __forceinline__ void walk_xy(const ProjParams &P, const Column &c, Bo
     flush();
 }
 
-template <int R, int MODE, bool STEEP>
+// The same walk read from the column's precomputed table (bit-identical
+// cells and parameters); the entries of the next 8 cells are loaded while the
+// current ones are processed.
+template <class Body, class Flush>
+__device__ __forceinline__ void walk_table(const ProjParams &P, int64_t col, Body &&body, Flush &&flush)
+{
+    const WalkHead h = P.walk_head[col];
+    const WalkEntry *e = P.walk_ent + col * P.walk_stride;
+    constexpr int B = 8;
+    float scur = h.s_in;
+    int k = 0;
+    WalkEntry next[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) next[j] = e[min(j, P.walk_stride - 1)];
+    for (int c0 = 0; c0 < h.n; c0 += B) {
+        WalkEntry cur[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) cur[j] = next[j];
+        if (c0 + B < h.n) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) next[j] = e[min(c0 + B + j, P.walk_stride - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (c0 + j >= h.n) break;
+            body((int64_t)cur[j].cell * P.nz, scur, cur[j].snext);
+            if (++k == FLUSH) {
+                flush();
+                k = 0;
+            }
+            scur = cur[j].snext;
+        }
+    }
+    flush();
+}
+
+// One thread per detector column: record the column's walk (the same walk_xy).
+__global__ void k_walk_table(const ProjParams P, int64_t n_cols, WalkHead *__restrict__ head,
+                             WalkEntry *__restrict__ ent)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_cols) return;
+    Column c;
+    WalkHead h{0, 0.0f};
+    if (column_setup(P, (int)(i / P.nu), (int)(i % P.nu), c)) {
+        h.s_in = (float)c.s_in;
+        WalkEntry *e = ent + i * P.walk_stride;
+        int n = 0;
+        walk_xy(P, c, [&](int64_t off, float, float snext) {
+            e[n].cell = (int32_t)(off / P.nz);
+            e[n].snext = snext;
+            ++n;
+        }, [] {});
+        h.n = n;
+    }
+    head[i] = h;
+}
+
+template <int R, int MODE, bool STEEP, bool WT>
 __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float *__restrict__ vol,
                                                  const float *__restrict__ lam, const float *__restrict__ y,
                                                  float *__restrict__ out, double *__restrict__ partial)
@@ -382,7 +440,7 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
                     acc32[r] = 0.0f;
                 }
             };
-            walk_xy(P, c, [&](int64_t off, float scur, float snext) {
+            auto cell_body = [&](int64_t off, float scur, float snext) {
                 const float *colp = volf + off;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -418,7 +476,9 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
                         ray_advance(z[r], q[r], 0.5 * P.nz);
                     }
                 }
-            }, flush);
+            };
+            if (WT) walk_table(P, (int64_t)T.view * P.nu + T.iu, cell_body, flush);
+            else walk_xy(P, c, cell_body, flush);
         }
         const int64_t base = (int64_t)T.view * P.nu * P.nv + (int64_t)T.iu * P.nv;
 #pragma unroll
@@ -808,17 +868,25 @@ __global__ void k_prescale(float *__restrict__ sino, const float *__restrict__ s
         sino[i] *= scale[i % per_view];
 }
 
+template <int R, bool STEEP, bool WT>
+hipError_t fwd_dispatch_wt(const ProjParams &pp, int mode, dim3 grid, dim3 block, const float *vol,
+                           const float *lam, const float *y, float *out, double *part, hipStream_t s)
+{
+    switch (mode) {
+    case PM_PLAIN: hipLaunchKernelGGL((k_forward<R, PM_PLAIN, STEEP, WT>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    case PM_WEIGHTED: hipLaunchKernelGGL((k_forward<R, PM_WEIGHTED, STEEP, WT>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    case PM_COUNT: hipLaunchKernelGGL((k_forward<R, PM_COUNT, STEEP, WT>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    default: hipLaunchKernelGGL((k_forward<R, PM_RESID, STEEP, WT>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
+    }
+    return hipGetLastError();
+}
+
 template <int R, bool STEEP>
 hipError_t fwd_dispatch_mode(const ProjParams &pp, int mode, dim3 grid, dim3 block, const float *vol,
                              const float *lam, const float *y, float *out, double *part, hipStream_t s)
 {
-    switch (mode) {
-    case PM_PLAIN: hipLaunchKernelGGL((k_forward<R, PM_PLAIN, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
-    case PM_WEIGHTED: hipLaunchKernelGGL((k_forward<R, PM_WEIGHTED, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
-    case PM_COUNT: hipLaunchKernelGGL((k_forward<R, PM_COUNT, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
-    default: hipLaunchKernelGGL((k_forward<R, PM_RESID, STEEP>), grid, block, 0, s, pp, vol, lam, y, out, part); break;
-    }
-    return hipGetLastError();
+    if (pp.walk_head) return fwd_dispatch_wt<R, STEEP, true>(pp, mode, grid, block, vol, lam, y, out, part, s);
+    return fwd_dispatch_wt<R, STEEP, false>(pp, mode, grid, block, vol, lam, y, out, part, s);
 }
 
 }  // namespace
@@ -845,6 +913,9 @@ ProjParams msf_plan::proj_params(bool with_active) const
     pp.cell_hdr = d_cell_hdr;
     pp.cell_ent = d_cell_ent;
     pp.cell_k = cell_k;
+    pp.walk_head = tiles.back_mode == 2 ? d_walk_head : nullptr;
+    pp.walk_ent = d_walk_ent;
+    pp.walk_stride = nx + ny + 2;
     pp.cols = d_cols;
     pp.g_zpl = std::min(4, (nz + WAVE - 1) / WAVE);   // one wave per voxel column up to nz = 256
     pp.scale = d_scale;
@@ -946,6 +1017,16 @@ hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s)
     U.consts = P.consts;
     U.part = P.part_g;
     return gather_launch<true>(P, pp, grid, block, s, P.sz, nullptr, U);
+}
+
+hipError_t launch_walk_table(msf_plan &P, hipStream_t s)
+{
+    ProjParams pp = P.proj_params(false);
+    const int64_t n = P.n_views * P.nu;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walk_table, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, pp, n, P.d_walk_head,
+                       P.d_walk_ent);
+    return hipGetLastError();
 }
 
 hipError_t launch_cell_table(msf_plan &P, hipStream_t s)
