@@ -65,3 +65,55 @@ def test_plane_smoothers_are_proximal_maps():
     # a constant field away from the boundary is preserved (taps sum to one)
     x = np.ones((1, 9, 9, 9))
     assert abs(mace.plane_smoother(x, 1, 1.0)[0, 4, 4, 4] - 1.0) < 1e-14
+
+
+def test_slices_round_trip_and_neighbour_mean():
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal((5, 3, 4, 6))
+    for k in (1, 2, 3):
+        S = mace.to_slices(W, k)
+        assert np.array_equal(mace.from_slices(S, k, W.shape), W)
+    # plane 2 images are (z, y) at fixed (t, x); plane 3 images are (z, x) at fixed (t, y)
+    S2 = mace.to_slices(W, 2).reshape(5, 6, 3, 4)
+    assert S2[1, 5, 2, 3] == W[1, 2, 3, 5]
+    S3 = mace.to_slices(W, 3).reshape(5, 4, 3, 6)
+    assert S3[4, 1, 0, 2] == W[4, 0, 1, 2]
+    m = mace.time_neighbour_mean(W)
+    assert np.allclose(m[2], (W[0] + W[1] + W[3] + W[4]) / 4)
+    assert np.allclose(m[0], (W[0] + W[0] + W[1] + W[2]) / 4)       # clamped at the ends
+
+
+def test_cnn_agent_with_identity_network():
+    """A network whose output is zero (last layer zero) is the identity agent; a
+    network that outputs its second input channel averages over time."""
+    from oracle import cnn
+    rng = np.random.default_rng(4)
+    W = rng.uniform(0, 1, (4, 3, 5, 6))
+    params = cnn.init_params(1)
+    params[3] = (np.zeros_like(params[3][0]), np.zeros_like(params[3][1]))
+    for k in (1, 2, 3):
+        assert np.allclose(mace.cnn_agent(W, k, params, (1.0, 1.0, 1.0)), cnn.bf16_round(W) * 0 + W, atol=0)
+
+
+def test_cnn_agent_centre_tap_network_closed_form():
+    """A network that only passes its two channels through the centre tap and
+    outputs alpha (channel 1 - channel 0) gives H(W) = W + alpha (mean_t W - W):
+    the time-neighbour channel and the residual output are wired as stated."""
+    from oracle import cnn
+    rng = np.random.default_rng(5)
+    W = rng.uniform(0.1, 1.0, (5, 3, 4, 6))
+    alpha = 0.25
+    params = []
+    for li, (ci, co) in enumerate(zip(cnn.CHANNELS[:-1], cnn.CHANNELS[1:])):
+        w = np.zeros((co, ci, 3, 3, 3))
+        if li < 3:
+            w[0, 0, 1, 1, 1] = 1.0
+            w[1, 1, 1, 1, 1] = 1.0
+        else:
+            w[0, 0, 1, 1, 1] = -alpha
+            w[0, 1, 1, 1, 1] = alpha
+        params.append((w, np.zeros(co)))
+    want = W + alpha * (mace.time_neighbour_mean(W) - W)
+    for k in (1, 2, 3):
+        got = mace.cnn_agent(W, k, params, (1.0, 1.0, 1.0))
+        assert np.allclose(got, want, rtol=0, atol=1e-2 * alpha), k     # inputs rounded to bf16
