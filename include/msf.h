@@ -180,29 +180,63 @@ msf_status msf_prox_solve(msf_plan *plan, const float *v, const float *y, const 
 msf_status msf_prox_features(msf_plan *plan, const float *v, const float *y, const float *lambda, double sigma,
                              float *g_out, void *stream);
 
-/* ---- learned warm start (not from the paper; plain CG stays the judge) ----
- * Network: 3D CNN, 3x3x3 kernels, channels 2 -> 16 -> 16 -> 16 -> 1, ReLU
- * after the first three layers, zero "same" padding:
+/* ---- the two networks (BF16 weights and activations on the matrix cores,
+ * FP32 accumulation, FP32 master parameters; zero "same" padding) ----
+ *
+ * MSF_CNN_WARM_START (msf_cnn_create; not from the paper, plain CG stays the
+ * judge of its prediction): 3D CNN, 3x3x3 kernels, channels 2 -> 16 -> 16 ->
+ * 16 -> 1, ReLU after the first three layers,
  *     x0 = v + c_o * f(v / c_v, g / c_g)
- * with g the feature above and scales (c_v, c_g, c_o).  Parameters are FP32
- * (15169 values: per layer W[out][in][3][3][3] then b[out]); the kernels use
- * BF16 weights and activations on the matrix cores with FP32 accumulation. */
+ * with g the feature above and scales (c_v, c_g, c_o).  15169 parameters:
+ * per layer W[out][in][3][3][3] then b[out].
+ *
+ * MSF_CNN_DENOISER (msf_cnn_create_denoiser): the 2.5D denoiser of the
+ * multi-slice fusion prior agents (paper Sec. IV): a 2D CNN, 3x3 kernels,
+ * channels 5 -> 16 -> 16 -> 16 -> 1, ReLU after the first three layers,
+ * whose five input channels are one 2D slice at the time points t-2, t-1,
+ * t, t+1, t+2 and whose output is the denoised centre slice
+ *     x_t = s_t + c_o * f(s_{t-2} / c_in, ..., s_{t+2} / c_in)
+ * with scales (c_in, c_o).  5521 parameters: per layer W[out][in][3][3]
+ * (kernel rows along the image's first axis) then b[out]. */
+enum { MSF_CNN_WARM_START = 0, MSF_CNN_DENOISER = 1 };
+
 msf_status msf_cnn_create(const float *params_host, int64_t n_params, const float *scales_host /* [3] */,
                           msf_cnn **out);
+msf_status msf_cnn_create_denoiser(const float *params_host, int64_t n_params, const float *scales_host /* [2] */,
+                                   msf_cnn **out);
 void msf_cnn_destroy(msf_cnn *cnn);
-/* Current FP32 parameters (host [15169]). */
+/* MSF_CNN_WARM_START or MSF_CNN_DENOISER (-1 for NULL). */
+int32_t msf_cnn_kind(const msf_cnn *cnn);
+/* 15169 or 5521 (0 for NULL). */
+int64_t msf_cnn_n_params(const msf_cnn *cnn);
+/* Current FP32 parameters (host [msf_cnn_n_params]). */
 msf_status msf_cnn_get_params(const msf_cnn *cnn, float *params_host);
-/* x0 = v + c_o f(v/c_v, g/c_g) for n volumes [n][nz][ny][nx] (device FP32). */
+/* The network on n images [nz][ny][nx] (device FP32), out x0 [n][nz][ny][nx].
+ * Warm start: v and g are volumes [n][nz][ny][nx].  Denoiser: nz = 1, v is
+ * the stacked input [n][5][ny][nx] (time points t-2 .. t+2) and g is
+ * ignored (may be NULL); x0 = v[i][2] + c_o f. */
 msf_status msf_cnn_infer(msf_cnn *cnn, const float *v, const float *g, int32_t n, int32_t nz, int32_t ny,
                          int32_t nx, float *x0, void *stream);
-/* One training step on the mean squared error between x0(v, g) and target
- * (device FP32 volumes [n][nz][ny][nx]): forward, backward and, if apply,
- * one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr.
- * loss_out (host) receives the loss before the step; grad_out (host [15169],
- * may be NULL) the FP32 gradient.  Synchronises the stream. */
+/* One training step on the mean squared error between x0 (inputs as in
+ * msf_cnn_infer) and target (device FP32 [n][nz][ny][nx]): forward, backward
+ * and, if apply, one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with
+ * learning rate lr.  loss_out (host) receives the loss before the step;
+ * grad_out (host [msf_cnn_n_params], may be NULL) the FP32 gradient.
+ * Synchronises the stream. */
 msf_status msf_cnn_train_step(msf_cnn *cnn, const float *v, const float *g, const float *target, int32_t n,
                               int32_t nz, int32_t ny, int32_t nx, double lr, int32_t apply, double *loss_out,
                               float *grad_out, void *stream);
+
+/* One prior agent of multi-slice fusion (paper Sec. IV): H_xy,t (plane 1),
+ * H_yz,t (plane 2) or H_zx,t (plane 3) applied to a 4D volume w [n_frames]
+ * [nz][ny][nx] (device FP32).  Every 2D slice of the plane (images (y, x) at
+ * fixed (t, z); (z, y) at fixed (t, x); (z, x) at fixed (t, y)) is replaced
+ * by the denoiser's output with the same slice at t-2 .. t+2 as input, time
+ * indices clamped to [0, n_frames).  cnn must be a MSF_CNN_DENOISER; out
+ * (device, [n_frames][nz][ny][nx]) must not overlap w.  Planes 2 and 3
+ * allocate two volumes of workspace for the call and synchronise. */
+msf_status msf_denoise25(msf_cnn *cnn, const float *w, int32_t n_frames, int32_t nz, int32_t ny, int32_t nx,
+                         int32_t plane, float *out, void *stream);
 
 /* ---- multi-agent consensus equilibrium around the proximal map ----
  * Algorithm 1 of the paper (partial-update Mann iteration, Sec. III):
@@ -211,16 +245,18 @@ msf_status msf_cnn_train_step(msf_cnn *cnn, const float *v, const float *g, cons
  * average W_0/(1+beta) + beta/(1+beta) mean_k W_k (eqs. (mace_G), (mace_avg)).
  * L~ is msf_prox_solve on W_0 started from the previous X_0: to tol (full
  * proximal map, partial_iters = 0) or for partial_iters CG steps (the paper's
- * partial update).  The paper's CNN denoisers are not available; the prior
- * agents are stand-ins that are proximal maps: MSF_PRIOR_PLANE_GAUSS = the
- * symmetric Gaussian smoother (std prior_param voxels, 7 taps, zero outside)
- * within the xy, yz and zx planes; MSF_PRIOR_RIDGE = x / (1 + prior_param
- * sigma^2), the proximal map of (prior_param / 2) ||x||^2. */
-enum { MSF_PRIOR_PLANE_GAUSS = 0, MSF_PRIOR_RIDGE = 1 };
+ * partial update).  Prior agents: MSF_PRIOR_CNN = the paper's multi-slice
+ * fusion agents H_xy,t, H_yz,t, H_zx,t (Sec. IV), msf_denoise25 in planes 1,
+ * 2 and 3 with the denoiser opts.prior_cnn.  Stand-ins that are true
+ * proximal maps: MSF_PRIOR_PLANE_GAUSS = the symmetric Gaussian smoother (std
+ * prior_param voxels, 7 taps, zero outside) within the xy, yz and zx planes;
+ * MSF_PRIOR_RIDGE = x / (1 + prior_param sigma^2), the proximal map of
+ * (prior_param / 2) ||x||^2. */
+enum { MSF_PRIOR_PLANE_GAUSS = 0, MSF_PRIOR_RIDGE = 1, MSF_PRIOR_CNN = 2 };
 
 typedef struct msf_mace_opts {
     int32_t n_iter;              /* Mann iterations (10 in the paper's experiments) */
-    int32_t prior;               /* MSF_PRIOR_PLANE_GAUSS or MSF_PRIOR_RIDGE */
+    int32_t prior;               /* MSF_PRIOR_PLANE_GAUSS, MSF_PRIOR_RIDGE or MSF_PRIOR_CNN */
     int32_t partial_iters;       /* 0: full solves; k > 0: k CG steps per outer iteration */
     int32_t max_iter;            /* CG step cap of a full solve */
     double beta;                 /* prior weight (1 = equal weighting) */
@@ -228,6 +264,7 @@ typedef struct msf_mace_opts {
     double prior_param;          /* Gaussian std (voxels) or ridge lambda */
     double tol;                  /* relative residual of a full solve */
     const msf_cnn *cnn;          /* optional learned start of the first solve */
+    const msf_cnn *prior_cnn;    /* MSF_PRIOR_CNN: the 2.5D denoiser (a MSF_CNN_DENOISER network) */
 } msf_mace_opts;
 
 typedef struct msf_mace_stats {
@@ -243,8 +280,8 @@ void msf_mace_opts_default(msf_mace_opts *opts);
 /* Runs the MACE loop on the plan's 4D volume.  x_init: device volume (the
  * initial reconstruction x^(0)) or NULL for zeros; y, lambda: device
  * sinograms; x_out: device volume (the final X_0).  Allocates 9 volumes of
- * workspace for the call.  Returns MSF_NOT_CONVERGED if a full solve hit
- * max_iter. */
+ * workspace for the call (11 with MSF_PRIOR_CNN).  Returns MSF_NOT_CONVERGED
+ * if a full solve hit max_iter. */
 msf_status msf_mace_run(msf_plan *plan, const float *x_init, const float *y, const float *lambda, double sigma,
                         const msf_mace_opts *opts, float *x_out, msf_mace_stats *stats, void *stream);
 

@@ -46,6 +46,8 @@ def conv3d(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
     xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1), (1, 1)))
     out = np.zeros((B, w.shape[0], Z, Y, X)) + b[None, :, None, None, None]
     for dz, dy, dx in TAPS:
+        if not w[:, :, dz, dy, dx].any():
+            continue        # an all-zero tap adds nothing
         patch = xp[:, :, dz:dz + Z, dy:dy + Y, dx:dx + X]
         out += np.einsum("oc,bczyx->bozyx", w[:, :, dz, dy, dx], patch)
     return out
@@ -88,7 +90,12 @@ def forward(params, inp: np.ndarray, bf16: bool = False, scale=1.0):
     Returns (x0 [B,1,Z,Y,X], cache)."""
     rnd = bf16_round if bf16 else (lambda a: a)
     cv, cg, co = (scale, scale, scale) if np.isscalar(scale) else scale
-    h = rnd(np.concatenate([inp[:, 0:1] / cv, inp[:, 1:2] / cg], axis=1))
+    f, cache = _layers(params, rnd(np.concatenate([inp[:, 0:1] / cv, inp[:, 1:2] / cg], axis=1)), rnd)
+    return inp[:, 0:1] + co * f, {"layers": cache, "bf16": bf16, "scale": co}
+
+
+def _layers(params, h, rnd):
+    """The four layers on the (already scaled and rounded) input h."""
     cache = []
     for li, (w, b) in enumerate(params):
         wq = rnd(w)
@@ -98,7 +105,7 @@ def forward(params, inp: np.ndarray, bf16: bool = False, scale=1.0):
             h = rnd(np.maximum(a, 0.0))
         else:
             h = a
-    return inp[:, 0:1] + co * h, {"layers": cache, "bf16": bf16, "scale": co}
+    return h, cache
 
 
 def backward(params, cache, dx0: np.ndarray):
@@ -164,3 +171,68 @@ def unflatten(vec: np.ndarray):
 
 def n_params() -> int:
     return sum(CHANNELS[i + 1] * (CHANNELS[i] * 27 + 1) for i in range(4))
+
+
+# ---------------------------------------------------------------------------
+# The 2.5D denoiser of the multi-slice fusion prior agents (paper Sec. IV):
+# the same four layers as a 2D network, 3x3 kernels, channels 5 -> 16 -> 16
+# -> 16 -> 1; its five input channels are one 2D slice at time points t-2,
+# t-1, t, t+1, t+2 and its output is the denoised centre slice
+#     x_t = s_t + c_o f(s_{t-2} / c_in, ..., s_{t+2} / c_in).
+# A 2D cross-correlation of an image is the 3D one of the same image as a
+# depth-1 volume with the 3x3 kernel as the depth-centre taps of a 3x3x3
+# kernel (the other depth taps only ever see the zero padding), so the
+# denoiser is evaluated with the functions above on such embedded kernels.
+# ---------------------------------------------------------------------------
+
+DENOISER_CHANNELS = (5, 16, 16, 16, 1)
+
+
+def den_embed(params2d):
+    """[(W [co][ci][3][3], b)] -> the equivalent 3x3x3 kernels (depth-centre taps)."""
+    out = []
+    for w, b in params2d:
+        w3 = np.zeros(w.shape[:2] + (3, 3, 3))
+        w3[:, :, 1] = w
+        out.append((w3, b))
+    return out
+
+
+def den_forward(params2d, stack: np.ndarray, bf16: bool = False, scale=(1.0, 1.0)):
+    """stack [B, 5, H, W] = one slice at t-2 .. t+2 (unscaled); scale (c_in, c_o).
+    Returns (x [B, H, W], cache)."""
+    rnd = bf16_round if bf16 else (lambda a: a)
+    c_in, c_o = scale
+    f, cache = _layers(den_embed(params2d), rnd(stack[:, :, None] / c_in), rnd)
+    return stack[:, 2] + c_o * f[:, 0, 0], {"layers": cache, "bf16": bf16, "scale": c_o}
+
+
+def den_backward(params2d, cache, dx: np.ndarray):
+    """Gradients w.r.t. every (W [co][ci][3][3], b) given d loss / d x [B, H, W]."""
+    grads = backward(den_embed(params2d), cache, dx[:, None, None])
+    return [(gw[:, :, 1], gb) for gw, gb in grads]
+
+
+def den_init_params(seed: int = 0, scale: float = 1.0):
+    """He-normal 3x3 weights, zero biases; the last layer starts small."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for li in range(4):
+        ci, co = DENOISER_CHANNELS[li], DENOISER_CHANNELS[li + 1]
+        std = np.sqrt(2.0 / (ci * 9)) * scale * (0.1 if li == 3 else 1.0)
+        params.append((rng.standard_normal((co, ci, 3, 3)) * std, np.zeros(co)))
+    return params
+
+
+def den_unflatten(vec: np.ndarray):
+    out, o = [], 0
+    for li in range(4):
+        ci, co = DENOISER_CHANNELS[li], DENOISER_CHANNELS[li + 1]
+        nw = co * ci * 9
+        out.append((vec[o:o + nw].reshape(co, ci, 3, 3).astype(np.float64), vec[o + nw:o + nw + co].astype(np.float64)))
+        o += nw + co
+    return out
+
+
+def den_n_params() -> int:
+    return sum(DENOISER_CHANNELS[i + 1] * (DENOISER_CHANNELS[i] * 9 + 1) for i in range(4))

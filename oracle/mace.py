@@ -75,52 +75,45 @@ def plane_smoother(x: np.ndarray, k: int, std: float) -> np.ndarray:
 
 # ---------------------------------------------------------------------------
 # 2.5D CNN denoiser agents (Sec. IV): one trained network applied slice by
-# slice in the xy, yz and zx planes, with neighbouring time points as input.
-# Reading: the network is the library's 4-layer CNN run on single slices
-# (depth 1, so its 3x3x3 kernels act as 3x3 kernels) with two input channels,
-# the slice itself and the mean of the same slice at time points t-2, t-1,
-# t+1, t+2 (indices clamped to the sequence); output = slice + c_o f.
+# slice in the xy, yz and zx planes, its channels the same slice at five
+# neighbouring time points, its output the denoised centre slice.
 # Plane k = 1: images (y, x) per (t, z); k = 2: images (z, y) per (t, x);
-# k = 3: images (z, x) per (t, y).
+# k = 3: images (z, x) per (t, y).  Reading: at the first and last two time
+# points the missing neighbours repeat the end frame (indices clamped).
 # ---------------------------------------------------------------------------
 
-def time_neighbour_mean(W: np.ndarray) -> np.ndarray:
-    """Mean of frames t-2, t-1, t+1, t+2 (clamped) for every frame of W [T][Z][Y][X]."""
-    T = W.shape[0]
-    out = np.zeros_like(W, dtype=np.float64)
-    for t in range(T):
-        for d in (-2, -1, 1, 2):
-            out[t] += W[min(max(t + d, 0), T - 1)]
-    return out / 4.0
-
-
 def to_slices(W: np.ndarray, k: int) -> np.ndarray:
-    """[T][Z][Y][X] -> images [T * n_slices][1][1][h][w] of plane k."""
-    T, Z, Y, X = W.shape
+    """[T][Z][Y][X] -> images [T][n_slices][h][w] of plane k."""
     if k == 1:
-        a = W                                   # [T][Z][Y][X]: images (y, x)
-    elif k == 2:
-        a = np.transpose(W, (0, 3, 1, 2))       # [T][X][Z][Y]: images (z, y)
-    else:
-        a = np.transpose(W, (0, 2, 1, 3))       # [T][Y][Z][X]: images (z, x)
-    return a.reshape(-1, 1, 1, a.shape[2], a.shape[3])
-
-
-def from_slices(S: np.ndarray, k: int, shape) -> np.ndarray:
-    """Inverse of to_slices."""
-    T, Z, Y, X = shape
-    if k == 1:
-        return S.reshape(T, Z, Y, X)
+        return W                                # [T][Z][Y][X]: images (y, x)
     if k == 2:
-        return np.transpose(S.reshape(T, X, Z, Y), (0, 2, 3, 1))
-    return np.transpose(S.reshape(T, Y, Z, X), (0, 2, 1, 3))
+        return np.transpose(W, (0, 3, 1, 2))    # [T][X][Z][Y]: images (z, y)
+    return np.transpose(W, (0, 2, 1, 3))        # [T][Y][Z][X]: images (z, x)
 
 
-def cnn_agent(W: np.ndarray, k: int, params, scales) -> np.ndarray:
+def from_slices(S: np.ndarray, k: int) -> np.ndarray:
+    """Inverse of to_slices."""
+    if k == 1:
+        return S
+    if k == 2:
+        return np.transpose(S, (0, 2, 3, 1))
+    return np.transpose(S, (0, 2, 1, 3))
+
+
+def time_stack(W: np.ndarray, k: int) -> np.ndarray:
+    """The denoiser inputs of plane k: [T * n_slices][5][h][w], channel c of
+    slice (t, s) being slice s at time clamp(t + c - 2)."""
+    S = to_slices(W, k)
+    T = S.shape[0]
+    chans = [S[[min(max(t + d, 0), T - 1) for t in range(T)]] for d in (-2, -1, 0, 1, 2)]
+    st = np.stack(chans, axis=2)                # [T][n_slices][5][h][w]
+    return st.reshape(-1, 5, S.shape[2], S.shape[3])
+
+
+def cnn_agent(W: np.ndarray, k: int, params2d, scales) -> np.ndarray:
     """H_k(W): the 2.5D denoiser in plane k (BF16 rounding at the GPU's points)."""
     from oracle import cnn
-    c = to_slices(W.astype(np.float64), k)
-    g = to_slices(time_neighbour_mean(W.astype(np.float64)), k)
-    x0, _ = cnn.forward(params, np.concatenate([c, g], axis=1), bf16=True, scale=scales)
-    return from_slices(x0, k, W.shape)
-
+    W = W.astype(np.float64)
+    x, _ = cnn.den_forward(params2d, time_stack(W, k), bf16=True, scale=scales)
+    S = to_slices(W, k)
+    return from_slices(x.reshape(S.shape), k)

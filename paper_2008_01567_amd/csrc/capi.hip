@@ -664,7 +664,10 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
         set_error("invalid solver options (tol >= 0, max_iter >= 0, check_every >= 1)"); return MSF_EINVAL;
     }
     if (o.x0_mode == MSF_X0_USER && !o.x0) { set_error("x0_mode USER needs x0"); return MSF_EINVAL; }
-    if (o.x0_mode == MSF_X0_CNN && !o.cnn) { set_error("x0_mode CNN needs a network"); return MSF_EINVAL; }
+    if (o.x0_mode == MSF_X0_CNN && (!o.cnn || cnn_kind(o.cnn) != MSF_CNN_WARM_START)) {
+        set_error("x0_mode CNN needs a warm-start network (msf_cnn_create)");
+        return MSF_EINVAL;
+    }
     if (o.x0_mode != MSF_X0_V && o.x0_mode != MSF_X0_USER && o.x0_mode != MSF_X0_CNN) {
         set_error("unknown x0_mode"); return MSF_EINVAL;
     }

@@ -1,16 +1,25 @@
-// Learned warm start of the proximal-map solve: a 4-layer 3D CNN
+// Two networks share these kernels.
+//
+// The learned warm start of the proximal-map solve: a 4-layer 3D CNN
 // (3x3x3 kernels, channels 2 -> 16 -> 16 -> 16 -> 1, ReLU after the first
 // three layers) predicting x0 = v + c_o f(v / c_v, g / c_g), where g is the
 // data term's backprojected weighted residual at v in voxel units and c_v,
-// c_g, c_o are fixed scales stored with the network.  The paper has no such network (its denoisers are 2.5D CNNs of
-// a different kind); plain CG remains the fallback and the judge of the
-// prediction.
+// c_g, c_o are fixed scales stored with the network.  The paper has no such
+// network; plain CG remains the fallback and the judge of the prediction.
+//
+// The 2.5D denoiser of the multi-slice fusion prior agents (paper Sec. IV):
+// the same four layers as a 2D network (3x3 kernels, channels 5 -> 16 -> 16
+// -> 16 -> 1) whose five input channels are one 2D slice at five adjacent
+// time points t-2 .. t+2 and whose output is the denoised centre slice,
+// x = s_t + c_o f(s_{t-2..t+2} / c_in).  Images are 2D (depth 1); the depth
+// taps of the 3D kernels are skipped.
 //
 // Every layer is an implicit GEMM on the matrix cores: channels-last BF16
-// activations [N][Z][Y][X][16] (the 2-channel input and the 1-channel output
-// are zero-padded to 16), and for each of the 27 taps one
+// activations [N][Z][Y][X][16] (the 2- or 5-channel input and the 1-channel
+// output are zero-padded to 16), and for each tap one
 // v_mfma_f32_16x16x16_bf16 multiplies 16 output voxels x 16 input channels by
-// the tap's 16 x 16 weight block, accumulating in FP32.  The input gradient is
+// the tap's 16 x 16 weight block, accumulating in FP32; taps that fall outside
+// the volume in y or z are skipped for the whole wave.  The input gradient is
 // the same kernel run with the spatially flipped, channel-transposed weights;
 // the weight gradient is a split-K MFMA GEMM over voxels with a fixed-order
 // reduction of the per-wave partial sums.  Master weights and Adam moments are
@@ -28,15 +37,44 @@ namespace {
 
 constexpr int CH = 16;
 constexpr int TAPS = 27;
-constexpr int NPARAM = 15169;
-constexpr int CIN[4] = {2, 16, 16, 16};
 constexpr int COUT[4] = {16, 16, 16, 1};
-constexpr int POFF[4] = {0, 880, 7808, 14736};   // offsets of W_l, b_l in the flat parameter vector
 constexpr int WPACK = TAPS * CH * CH;              // packed bf16 weights per layer
 constexpr int PART = TAPS * CH * CH + CH;          // weight-gradient partial per wave (+ bias)
 constexpr int WG_BLOCKS = 512;                     // blocks of the weight-gradient kernel
 
 enum Epi : int { EPI_RELU = 0, EPI_RESID = 1, EPI_MASK = 2 };
+
+// Parameter layout of a network: per layer W[out][in][taps] then b[out],
+// with taps = 27 (3x3x3) or 9 (3x3, the depth-centre taps of the kernels).
+struct NetShape {
+    int cin0;             // input channels of the first layer (2 or 5)
+    int ptaps;            // 27 or 9
+    int poff[4];          // offsets of W_l, b_l in the flat parameter vector
+    int nparam;
+};
+
+__host__ __device__ inline int net_cin(const NetShape &S, int layer) { return layer == 0 ? S.cin0 : CH; }
+
+// parameter tap of kernel tap (dz, dy, dx), or -1 for a depth tap of a 2D network
+__host__ __device__ inline int net_ptap(const NetShape &S, int tap)
+{
+    if (S.ptaps == TAPS) return tap;
+    return tap / 9 == 1 ? tap - 9 : -1;
+}
+
+NetShape make_shape(int cin0, int ptaps)
+{
+    NetShape S{};
+    S.cin0 = cin0;
+    S.ptaps = ptaps;
+    int o = 0;
+    for (int l = 0; l < 4; ++l) {
+        S.poff[l] = o;
+        o += COUT[l] * (net_cin(S, l) * ptaps + 1);
+    }
+    S.nparam = o;
+    return S;
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -54,7 +92,8 @@ struct ConvArgs {
     uint16_t *out_bf;       // EPI_RELU / EPI_MASK
     const uint16_t *mask;   // EPI_MASK: gradient passes where this activation is > 0
     float *out_f;           // EPI_RESID: x0 [N][Z][Y][X]
-    const float *v;         // EPI_RESID
+    const float *v;         // EPI_RESID: residual base of image n at v + n * v_stride + v_off
+    int64_t v_stride, v_off;
     float scale;            // EPI_RESID
 };
 
@@ -77,18 +116,20 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
         const int n = (int)(t / A.Z);
         const int x0 = xs * 16;
         v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        // z and y are the same for the whole wave: taps outside the volume
+        // (zero inputs) are skipped, so depth-1 images run the 9 in-plane taps
         for (int dz = 0; dz < 3; ++dz) {
             const int zz = z + dz - 1;
-            const bool zok = zz >= 0 && zz < A.Z;
+            if (zz < 0 || zz >= A.Z) continue;
             for (int dy = 0; dy < 3; ++dy) {
                 const int yy = y + dy - 1;
-                const bool yok = zok && yy >= 0 && yy < A.Y;
+                if (yy < 0 || yy >= A.Y) continue;
                 const int64_t row = (((int64_t)n * A.Z + zz) * A.Y + yy) * A.X;
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
                     const int xx = x0 + r + dx - 1;
                     v4s a = {0, 0, 0, 0};
-                    if (yok && xx >= 0 && xx < A.X) a = *reinterpret_cast<const v4s *>(A.in + (row + xx) * CH + 4 * g);
+                    if (xx >= 0 && xx < A.X) a = *reinterpret_cast<const v4s *>(A.in + (row + xx) * CH + 4 * g);
                     const v4s b = wl[((dz * 3 + dy) * 3 + dx) * (CH * 4) + r * 4 + g];
                     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
                 }
@@ -97,6 +138,7 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
         // lane holds output voxel x0 + 4g + j, channel r
         const float bias = A.bias ? A.bias[r] : 0.0f;
         const int64_t vrow = (((int64_t)n * A.Z + z) * A.Y + y) * A.X;
+        const int64_t vbase = (int64_t)n * A.v_stride + A.v_off + ((int64_t)z * A.Y + y) * A.X;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int xv = x0 + 4 * g + j;
@@ -108,7 +150,7 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
             } else if (EPI == EPI_MASK) {
                 A.out_bf[vox * CH + r] = bf2f(A.mask[vox * CH + r]) > 0.0f ? f2bf(val) : (uint16_t)0;
             } else {
-                if (r == 0) A.out_f[vox] = A.v[vox] + A.scale * val;
+                if (r == 0) A.out_f[vox] = A.v[vbase + xv] + A.scale * val;
             }
         }
     }
@@ -151,11 +193,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs A)
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
             const int zz = z + dz - 1;
-            const bool zok = zz >= 0 && zz < A.Z;
+            if (zz < 0 || zz >= A.Z) continue;     // uniform over the wave: zero contribution
 #pragma unroll
             for (int dy = 0; dy < 3; ++dy) {
                 const int yy = y + dy - 1;
-                const bool yok = zok && yy >= 0 && yy < A.Y;
+                if (yy < 0 || yy >= A.Y) continue;
                 const int64_t row = (((int64_t)n * A.Z + zz) * A.Y + yy) * A.X;
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
@@ -164,7 +206,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs A)
                     for (int j = 0; j < 4; ++j) {
                         const int xv = x0 + 4 * g + j;
                         const int xx = xv + dx - 1;
-                        hb[j] = (short)((yok && xv < A.X && xx >= 0 && xx < A.X) ? A.h[(row + xx) * CH + r] : (uint16_t)0);
+                        hb[j] = (short)((xv < A.X && xx >= 0 && xx < A.X) ? A.h[(row + xx) * CH + r] : (uint16_t)0);
                     }
                     const int tap = (dz * 3 + dy) * 3 + dx;
                     acc[tap] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ga, hb, acc[tap], 0, 0, 0);
@@ -183,49 +225,88 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs A)
     if (g == 0) out[TAPS * CH * CH + r] = bsum;
 }
 
-// grad_flat[layer] <- sum of the per-wave partials (fixed order), real channels only
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwaves, int layer, float *__restrict__ grad)
+// grad_flat[layer] <- sum of the per-wave partials (fixed order), real channels
+// and parameter taps only
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwaves, int layer, const NetShape S,
+                               float *__restrict__ grad)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= PART) return;
-    float s = 0.0f;
-    for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * PART + e];
-    const int cin = CIN[layer], cout = COUT[layer];
+    const int cin = net_cin(S, layer), cout = COUT[layer];
     if (e < TAPS * CH * CH) {
         const int tap = e / (CH * CH), o = (e / CH) % CH, i = e % CH;
-        if (o < cout && i < cin) grad[POFF[layer] + (o * cin + i) * TAPS + tap] = s;
+        const int pt = net_ptap(S, tap);
+        if (o >= cout || i >= cin || pt < 0) return;
+        float s = 0.0f;
+        for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * PART + e];
+        grad[S.poff[layer] + (o * cin + i) * S.ptaps + pt] = s;
     } else {
         const int o = e - TAPS * CH * CH;
-        if (o < cout) grad[POFF[layer] + cout * cin * TAPS + o] = s;
+        if (o >= cout) return;
+        float s = 0.0f;
+        for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * PART + e];
+        grad[S.poff[layer] + cout * cin * S.ptaps + o] = s;
     }
 }
 
 // bf16 weights for the forward ([tap][out][in]) and the input gradient
 // (flipped taps, in/out swapped), FP32 biases padded to 16
-__global__ void k_pack(const float *__restrict__ master, uint16_t *__restrict__ wf, uint16_t *__restrict__ wd,
-                       float *__restrict__ bias)
+__global__ void k_pack(const float *__restrict__ master, const NetShape S, uint16_t *__restrict__ wf,
+                       uint16_t *__restrict__ wd, float *__restrict__ bias)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 4 * WPACK) return;
     const int layer = e / WPACK, k = e % WPACK;
     const int tap = k / (CH * CH), o = (k / CH) % CH, i = k % CH;
-    const int cin = CIN[layer], cout = COUT[layer];
-    const float *W = master + POFF[layer];
-    wf[e] = (o < cout && i < cin) ? f2bf(W[(o * cin + i) * TAPS + tap]) : (uint16_t)0;
+    const int cin = net_cin(S, layer), cout = COUT[layer];
+    const float *W = master + S.poff[layer];
+    const int pt = net_ptap(S, tap);
+    wf[e] = (o < cout && i < cin && pt >= 0) ? f2bf(W[(o * cin + i) * S.ptaps + pt]) : (uint16_t)0;
     // input gradient: out channel o' = forward input i', in channel i' = forward output o'
-    const int ftap = TAPS - 1 - tap;
-    wd[e] = (i < cout && o < cin) ? f2bf(W[(i * cin + o) * TAPS + ftap]) : (uint16_t)0;
-    if (k < CH) bias[layer * CH + k] = k < cout ? master[POFF[layer] + cout * cin * TAPS + k] : 0.0f;
+    const int fpt = net_ptap(S, TAPS - 1 - tap);
+    wd[e] = (i < cout && o < cin && fpt >= 0) ? f2bf(W[(i * cin + o) * S.ptaps + fpt]) : (uint16_t)0;
+    if (k < CH) bias[layer * CH + k] = k < cout ? master[S.poff[layer] + cout * cin * S.ptaps + k] : 0.0f;
 }
 
-// input channels: bf16(v / c_v), bf16(g / c_g), zeros
-__global__ void k_pack_input(const float *__restrict__ v, const float *__restrict__ gin, int64_t n, float inv_cv,
-                             float inv_cg, uint16_t *__restrict__ h0)
+// Sources of the input channels of images [n0, n0 + n / per):
+//   IN_WARM:  channel 0 = a / c_v, channel 1 = g / c_g (volumes [img][per]);
+//   IN_STACK: channel c = a[img][c][per] / c_in, c < 5;
+//   IN_SEQ:   a is a sequence [T][S][per] of S images per time point; image
+//             t S + s has channel c = the same image at time clamp(t + c - 2)
+//             / c_in, c < 5 (time points t-2 .. t+2, repeated at the ends).
+enum InMode : int { IN_WARM = 0, IN_STACK = 1, IN_SEQ = 2 };
+
+struct PackIn {
+    int mode;
+    const float *a, *g;
+    int64_t n0;           // first image (IN_SEQ)
+    int T, S;             // IN_SEQ
+    float inv0, inv1;
+};
+
+__device__ __forceinline__ float pack_src(const PackIn &P, int64_t img, int64_t loc, int c, int64_t per)
 {
+    if (P.mode == IN_WARM) return c == 0 ? P.a[img * per + loc] : P.g[img * per + loc];
+    if (P.mode == IN_STACK) return P.a[(img * 5 + c) * per + loc];
+    const int64_t gi = P.n0 + img;
+    const int t = (int)(gi / P.S), si = (int)(gi - (int64_t)t * P.S);
+    const int tt = min(max(t + c - 2, 0), P.T - 1);
+    return P.a[((int64_t)tt * P.S + si) * per + loc];
+}
+
+__global__ void k_pack_input(const PackIn P, int64_t n, int64_t per, uint16_t *__restrict__ h0)
+{
+    const int cin = P.mode == IN_WARM ? 2 : 5;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * CH; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t vox = e / CH;
         const int c = (int)(e % CH);
-        h0[e] = c == 0 ? f2bf(v[vox] * inv_cv) : (c == 1 ? f2bf(gin[vox] * inv_cg) : (uint16_t)0);
+        uint16_t h = 0;
+        if (c < cin) {
+            const int64_t img = vox / per;
+            const float sc = (P.mode == IN_WARM && c == 1) ? P.inv1 : P.inv0;
+            h = f2bf(pack_src(P, img, vox - img * per, c, per) * sc);
+        }
+        h0[e] = h;
     }
 }
 
@@ -280,7 +361,9 @@ unsigned grid_of(int64_t work, int per_block)
 }  // namespace
 
 struct msf_cnn {
-    float cv = 1.0f, cg = 1.0f, co = 1.0f;   // input / feature / output scales
+    NetShape shape{};
+    int kind = MSF_CNN_WARM_START;
+    float cv = 1.0f, cg = 1.0f, co = 1.0f;   // input / feature / output scales (denoiser: cv = c_in)
     float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     uint16_t *wf = nullptr, *wd = nullptr;
     float *bias = nullptr;
@@ -334,9 +417,10 @@ hipError_t cnn_reserve(msf_cnn *C, int64_t nvox)
 }
 
 hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const float *bias, int N, int Z, int Y, int X,
-                       uint16_t *out_bf, const uint16_t *mask, float *out_f, const float *v, float scale, hipStream_t s)
+                       uint16_t *out_bf, const uint16_t *mask, float *out_f, const float *v, int64_t v_stride,
+                       int64_t v_off, float scale, hipStream_t s)
 {
-    ConvArgs A{in, w, bias, N, Z, Y, X, out_bf, mask, out_f, v, scale};
+    ConvArgs A{in, w, bias, N, Z, Y, X, out_bf, mask, out_f, v, v_stride, v_off, scale};
     const int64_t nseg = (int64_t)N * Z * Y * ((X + 15) / 16);
     const dim3 grid(grid_of(nseg, 4)), block(256);
     switch (epi) {
@@ -347,26 +431,83 @@ hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const flo
     return hipGetLastError();
 }
 
-hipError_t cnn_forward(msf_cnn *C, const float *v, const float *gin, int N, int Z, int Y, int X, float *x0,
-                       hipStream_t s)
+// Forward pass of N images [Z][Y][X] whose input channels come from `in`;
+// x0 = residual base + c_o f, the base of image n at vbase + n v_stride + v_off.
+hipError_t cnn_forward(msf_cnn *C, const PackIn &in, int N, int Z, int Y, int X, const float *vbase, int64_t v_stride,
+                       int64_t v_off, float *x0, hipStream_t s)
 {
-    const int64_t n = (int64_t)N * Z * Y * X;
+    const int64_t per = (int64_t)Z * Y * X, n = (int64_t)N * per;
     hipError_t e;
-    hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n * CH, 256)), dim3(256), 0, s, v, gin, n, 1.0f / C->cv,
-                       1.0f / C->cg, C->h[0]);
+    hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n * CH, 256)), dim3(256), 0, s, in, n, per, C->h[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int l = 0; l < 3; ++l)
         if ((e = launch_conv(EPI_RELU, C->h[l], C->wf + l * WPACK, C->bias + l * CH, N, Z, Y, X, C->h[l + 1],
-                             nullptr, nullptr, nullptr, 0.0f, s)) != hipSuccess)
+                             nullptr, nullptr, nullptr, 0, 0, 0.0f, s)) != hipSuccess)
             return e;
-    return launch_conv(EPI_RESID, C->h[3], C->wf + 3 * WPACK, C->bias + 3 * CH, N, Z, Y, X, nullptr, nullptr, x0, v,
-                       C->co, s);
+    return launch_conv(EPI_RESID, C->h[3], C->wf + 3 * WPACK, C->bias + 3 * CH, N, Z, Y, X, nullptr, nullptr, x0,
+                       vbase, v_stride, v_off, C->co, s);
+}
+
+// the input of a caller's images: warm start (v, g) or the denoiser's stacked slices
+PackIn caller_input(const msf_cnn *C, const float *v, const float *g)
+{
+    PackIn P{};
+    P.mode = C->kind == MSF_CNN_WARM_START ? IN_WARM : IN_STACK;
+    P.a = v;
+    P.g = g;
+    P.inv0 = 1.0f / C->cv;
+    P.inv1 = 1.0f / C->cg;
+    return P;
 }
 
 hipError_t cnn_pack(msf_cnn *C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pack, dim3((4 * WPACK + 255) / 256), dim3(256), 0, s, C->master, C->wf, C->wd, C->bias);
+    hipLaunchKernelGGL(k_pack, dim3((4 * WPACK + 255) / 256), dim3(256), 0, s, C->master, C->shape, C->wf, C->wd,
+                       C->bias);
     return hipGetLastError();
+}
+
+// [T][Z][Y][X] <-> the plane-k sequence [T][S][H][W]: k = 2 -> [T][X][Z][Y]
+// (images (z, y) at fixed x), k = 3 -> [T][Y][Z][X] (images (z, x) at fixed y);
+// to = 1: volume -> sequence, to = 0: sequence -> volume
+__global__ void k_plane_transpose(const float *__restrict__ in, float *__restrict__ out, int T, int Z, int Y, int X,
+                                  int plane, int to)
+{
+    const int64_t n = (int64_t)T * Z * Y * X;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;    // volume index [t][z][y][x]
+        const int x = (int)(r % X); r /= X;
+        const int y = (int)(r % Y); r /= Y;
+        const int z = (int)(r % Z);
+        const int t = (int)(r / Z);
+        const int64_t q = plane == 2 ? (((int64_t)t * X + x) * Z + z) * Y + y : (((int64_t)t * Y + y) * Z + z) * X + x;
+        if (to) out[q] = in[i];
+        else out[i] = in[q];
+    }
+}
+
+// the denoiser on a plane sequence [T][S][H][W] (images chunked so that the
+// activations fit in 2^26 voxels); out must not overlap seq
+hipError_t denoise_sequence(msf_cnn *C, const float *seq, int T, int S, int H, int W, float *out, hipStream_t s)
+{
+    const int64_t per = (int64_t)H * W;
+    const int64_t N = (int64_t)T * S;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)1 << 26) / per));
+    hipError_t e = cnn_reserve(C, (int64_t)chunk * per);
+    if (e != hipSuccess) return e;
+    PackIn P{};
+    P.mode = IN_SEQ;
+    P.a = seq;
+    P.T = T;
+    P.S = S;
+    P.inv0 = 1.0f / C->cv;
+    for (int64_t f0 = 0; f0 < N; f0 += chunk) {
+        const int nf = (int)std::min<int64_t>(chunk, N - f0);
+        P.n0 = f0;
+        e = cnn_forward(C, P, nf, 1, H, W, seq + f0 * per, per, 0, out + f0 * per, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #define CHK(expr)                                            \
@@ -375,7 +516,71 @@ hipError_t cnn_pack(msf_cnn *C, hipStream_t s)
         if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
     } while (0)
 
+msf_status cnn_create(int kind, const float *params, int64_t n_params, const float *scales, msf_cnn **out)
+{
+    set_error("");
+    const NetShape S = kind == MSF_CNN_WARM_START ? make_shape(2, TAPS) : make_shape(5, 9);
+    const int nsc = kind == MSF_CNN_WARM_START ? 3 : 2;
+    if (!params || !out || !scales || n_params != S.nparam) {
+        set_error(kind == MSF_CNN_WARM_START ? "msf_cnn_create: need 15169 parameters and 3 scales"
+                                             : "msf_cnn_create_denoiser: need 5521 parameters and 2 scales");
+        return MSF_EINVAL;
+    }
+    for (int k = 0; k < nsc; ++k)
+        if (!(std::isfinite(scales[k]) && scales[k] > 0.0f)) {
+            set_error("msf_cnn_create: scales must be positive and finite");
+            return MSF_EINVAL;
+        }
+    for (int64_t i = 0; i < n_params; ++i)
+        if (!std::isfinite(params[i])) { set_error("msf_cnn_create: non-finite parameter"); return MSF_EINVAL; }
+    msf_cnn *C = new (std::nothrow) msf_cnn();
+    if (!C) { set_error("host allocation failed"); return MSF_ENOMEM; }
+    C->shape = S;
+    C->kind = kind;
+    if (kind == MSF_CNN_WARM_START) {
+        C->cv = scales[0];
+        C->cg = scales[1];
+        C->co = scales[2];
+    } else {
+        C->cv = C->cg = scales[0];
+        C->co = scales[1];
+    }
+    hipError_t e = hipSuccess;
+    auto fail = [&](hipError_t err) {
+        msf_cnn_destroy(C);
+        return hip_fail(err, "msf_cnn_create");
+    };
+    const int NP = S.nparam;
+    if ((e = cnn_alloc(&C->master, NP)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->m, NP)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->v, NP)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->grad, NP)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->wf, 4 * WPACK)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->wd, 4 * WPACK)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->bias, 4 * CH)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->part, (size_t)WG_BLOCKS * 4 * PART)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->lpart, 65536)) != hipSuccess) return fail(e);
+    if ((e = cnn_alloc(&C->flag, 4)) != hipSuccess) return fail(e);
+    if ((e = hipHostMalloc((void **)&C->hlpart, 65536 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return fail(e);
+    if ((e = hipMemcpy(C->master, params, NP * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+    if ((e = hipMemset(C->m, 0, NP * sizeof(float))) != hipSuccess) return fail(e);
+    if ((e = hipMemset(C->v, 0, NP * sizeof(float))) != hipSuccess) return fail(e);
+    if ((e = hipMemset(C->grad, 0, NP * sizeof(float))) != hipSuccess) return fail(e);
+    if ((e = cnn_pack(C, nullptr)) != hipSuccess) return fail(e);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(e);
+    *out = C;
+    return MSF_OK;
+}
+
+bool shape_ok(const msf_cnn *C, int32_t n, int32_t nz, int32_t ny, int32_t nx)
+{
+    if (n <= 0 || nz <= 0 || ny <= 0 || nx <= 0) return false;
+    return C->kind == MSF_CNN_WARM_START || nz == 1;
+}
+
 }  // namespace
+
+int cnn_kind(const msf_cnn *C) { return C->kind; }
 
 hipError_t cnn_io_buffers(msf_cnn *C, int64_t n, float **g, float **x)
 {
@@ -395,64 +600,48 @@ hipError_t cnn_io_buffers(msf_cnn *C, int64_t n, float **g, float **x)
 hipError_t cnn_infer_internal(msf_cnn *C, const float *v, const float *g, int N, int Z, int Y, int X, float *x0,
                               hipStream_t s)
 {
-    // volumes are independent: evaluate them in chunks of at most 2^26 voxels
+    // images are independent: evaluate them in chunks of at most 2^26 voxels
     // (activations take 32 bytes per voxel and layer)
     const int64_t per = (int64_t)Z * Y * X;
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)1 << 26) / per));
     hipError_t e = cnn_reserve(C, (int64_t)chunk * per);
     if (e != hipSuccess) return e;
+    const bool stack = C->kind == MSF_CNN_DENOISER;
+    const int64_t in_img = stack ? 5 * per : per;     // input floats per image
     for (int f0 = 0; f0 < N; f0 += chunk) {
         const int nf = std::min(chunk, N - f0);
-        e = cnn_forward(C, v + f0 * per, g + f0 * per, nf, Z, Y, X, x0 + f0 * per, s);
+        const PackIn P = caller_input(C, v + f0 * in_img, stack ? nullptr : g + f0 * per);
+        e = cnn_forward(C, P, nf, Z, Y, X, v + f0 * in_img, in_img, stack ? 2 * per : 0, x0 + f0 * per, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t denoise25_internal(msf_cnn *C, const float *w, int T, int Z, int Y, int X, int plane, float *out,
+                              float *scratch_a, float *scratch_b, hipStream_t s)
+{
+    if (plane == 1) return denoise_sequence(C, w, T, Z, Y, X, out, s);
+    const int64_t n = (int64_t)T * Z * Y * X;
+    hipLaunchKernelGGL(k_plane_transpose, dim3(grid_of(n, 256)), dim3(256), 0, s, w, scratch_a, T, Z, Y, X, plane, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = plane == 2 ? denoise_sequence(C, scratch_a, T, X, Z, Y, scratch_b, s)
+                   : denoise_sequence(C, scratch_a, T, Y, Z, X, scratch_b, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plane_transpose, dim3(grid_of(n, 256)), dim3(256), 0, s, scratch_b, out, T, Z, Y, X, plane, 0);
+    return hipGetLastError();
 }
 
 extern "C" {
 
 msf_status msf_cnn_create(const float *params, int64_t n_params, const float *scales, msf_cnn **out)
 {
-    set_error("");
-    if (!params || !out || !scales || n_params != NPARAM) {
-        set_error("msf_cnn_create: need 15169 parameters and 3 scales");
-        return MSF_EINVAL;
-    }
-    for (int k = 0; k < 3; ++k)
-        if (!(std::isfinite(scales[k]) && scales[k] > 0.0f)) {
-            set_error("msf_cnn_create: scales must be positive and finite");
-            return MSF_EINVAL;
-        }
-    for (int64_t i = 0; i < n_params; ++i)
-        if (!std::isfinite(params[i])) { set_error("msf_cnn_create: non-finite parameter"); return MSF_EINVAL; }
-    msf_cnn *C = new (std::nothrow) msf_cnn();
-    if (!C) { set_error("host allocation failed"); return MSF_ENOMEM; }
-    C->cv = scales[0];
-    C->cg = scales[1];
-    C->co = scales[2];
-    hipError_t e = hipSuccess;
-    auto fail = [&](hipError_t err) {
-        msf_cnn_destroy(C);
-        return hip_fail(err, "msf_cnn_create");
-    };
-    if ((e = cnn_alloc(&C->master, NPARAM)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->m, NPARAM)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->v, NPARAM)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->grad, NPARAM)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->wf, 4 * WPACK)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->wd, 4 * WPACK)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->bias, 4 * CH)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->part, (size_t)WG_BLOCKS * 4 * PART)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->lpart, 65536)) != hipSuccess) return fail(e);
-    if ((e = cnn_alloc(&C->flag, 4)) != hipSuccess) return fail(e);
-    if ((e = hipHostMalloc((void **)&C->hlpart, 65536 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return fail(e);
-    if ((e = hipMemcpy(C->master, params, NPARAM * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
-    if ((e = hipMemset(C->m, 0, NPARAM * sizeof(float))) != hipSuccess) return fail(e);
-    if ((e = hipMemset(C->v, 0, NPARAM * sizeof(float))) != hipSuccess) return fail(e);
-    if ((e = cnn_pack(C, nullptr)) != hipSuccess) return fail(e);
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(e);
-    *out = C;
-    return MSF_OK;
+    return cnn_create(MSF_CNN_WARM_START, params, n_params, scales, out);
+}
+
+msf_status msf_cnn_create_denoiser(const float *params, int64_t n_params, const float *scales, msf_cnn **out)
+{
+    return cnn_create(MSF_CNN_DENOISER, params, n_params, scales, out);
 }
 
 void msf_cnn_destroy(msf_cnn *C)
@@ -467,10 +656,14 @@ void msf_cnn_destroy(msf_cnn *C)
     delete C;
 }
 
+int32_t msf_cnn_kind(const msf_cnn *C) { return C ? C->kind : -1; }
+
+int64_t msf_cnn_n_params(const msf_cnn *C) { return C ? C->shape.nparam : 0; }
+
 msf_status msf_cnn_get_params(const msf_cnn *C, float *params)
 {
     if (!C || !params) { set_error("null argument"); return MSF_EINVAL; }
-    CHK(hipMemcpy(params, C->master, NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    CHK(hipMemcpy(params, C->master, C->shape.nparam * sizeof(float), hipMemcpyDeviceToHost));
     return MSF_OK;
 }
 
@@ -478,8 +671,40 @@ msf_status msf_cnn_infer(msf_cnn *C, const float *v, const float *g, int32_t n, 
                          float *x0, void *stream)
 {
     set_error("");
-    if (!C || !v || !g || !x0 || n <= 0 || nz <= 0 || ny <= 0 || nx <= 0) { set_error("invalid argument"); return MSF_EINVAL; }
+    if (!C || !v || !x0 || (C->kind == MSF_CNN_WARM_START && !g) || !shape_ok(C, n, nz, ny, nx)) {
+        set_error("invalid argument (the denoiser takes images with nz = 1)");
+        return MSF_EINVAL;
+    }
     CHK(cnn_infer_internal(C, v, g, n, nz, ny, nx, x0, (hipStream_t)stream));
+    return MSF_OK;
+}
+
+msf_status msf_denoise25(msf_cnn *C, const float *w, int32_t n_frames, int32_t nz, int32_t ny, int32_t nx,
+                         int32_t plane, float *out, void *stream)
+{
+    set_error("");
+    if (!C || !w || !out || C->kind != MSF_CNN_DENOISER || n_frames <= 0 || nz <= 0 || ny <= 0 || nx <= 0 ||
+        plane < 1 || plane > 3) {
+        set_error("msf_denoise25: needs a denoiser network, a non-empty [n_frames][nz][ny][nx] volume, plane 1..3");
+        return MSF_EINVAL;
+    }
+    const int64_t n = (int64_t)n_frames * nz * ny * nx;
+    if (w < out + n && out < w + n) { set_error("msf_denoise25: out overlaps w"); return MSF_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    float *sa = nullptr, *sb = nullptr;
+    if (plane != 1) {
+        hipError_t e = hipMalloc((void **)&sa, sizeof(float) * n);
+        if (e == hipSuccess) e = hipMalloc((void **)&sb, sizeof(float) * n);
+        if (e != hipSuccess) {
+            if (sa) (void)hipFree(sa);
+            return hip_fail(e, "msf_denoise25 workspace");
+        }
+    }
+    hipError_t e = denoise25_internal(C, w, n_frames, nz, ny, nx, plane, out, sa, sb, s);
+    if (e == hipSuccess && plane != 1) e = hipStreamSynchronize(s);
+    if (sa) (void)hipFree(sa);
+    if (sb) (void)hipFree(sb);
+    if (e != hipSuccess) return hip_fail(e, "msf_denoise25");
     return MSF_OK;
 }
 
@@ -488,14 +713,17 @@ msf_status msf_cnn_train_step(msf_cnn *C, const float *v, const float *g, const 
                               void *stream)
 {
     set_error("");
-    if (!C || !v || !g || !target || n <= 0 || nz <= 0 || ny <= 0 || nx <= 0 || !(lr >= 0.0)) {
-        set_error("invalid argument");
+    if (!C || !v || !target || (C->kind == MSF_CNN_WARM_START && !g) || !shape_ok(C, n, nz, ny, nx) || !(lr >= 0.0)) {
+        set_error("invalid argument (the denoiser takes images with nz = 1)");
         return MSF_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
-    const int64_t nvox = (int64_t)n * nz * ny * nx;
+    const int64_t per = (int64_t)nz * ny * nx;
+    const int64_t nvox = (int64_t)n * per;
+    const bool stack = C->kind == MSF_CNN_DENOISER;
     CHK(cnn_reserve(C, nvox));
-    CHK(cnn_forward(C, v, g, n, nz, ny, nx, C->pred, s));
+    CHK(cnn_forward(C, caller_input(C, v, g), n, nz, ny, nx, v, stack ? 5 * per : per, stack ? 2 * per : 0, C->pred,
+                    s));
     const unsigned lb = grid_of(nvox, 256);
     hipLaunchKernelGGL(k_mse, dim3(lb), dim3(256), 0, s, C->pred, target, nvox, C->co, C->ga, C->lpart);
     CHK(hipGetLastError());
@@ -506,22 +734,23 @@ msf_status msf_cnn_train_step(msf_cnn *C, const float *v, const float *g, const 
         hipLaunchKernelGGL(k_wgrad, dim3(WG_BLOCKS), dim3(256), 0, s, W);
         CHK(hipGetLastError());
         hipLaunchKernelGGL(k_wgrad_reduce, dim3((PART + 255) / 256), dim3(256), 0, s, C->part, WG_BLOCKS * 4, l,
-                           C->grad);
+                           C->shape, C->grad);
         CHK(hipGetLastError());
         if (l > 0) {
             CHK(launch_conv(EPI_MASK, gcur, C->wd + l * WPACK, nullptr, n, nz, ny, nx, gnext, C->h[l], nullptr,
-                            nullptr, 0.0f, s));
+                            nullptr, 0, 0, 0.0f, s));
             std::swap(gcur, gnext);
         }
     }
+    const int NP = C->shape.nparam;
     CHK(hipMemcpyAsync(C->hlpart, C->lpart, lb * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (grad_out) CHK(hipMemcpyAsync(grad_out, C->grad, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    if (grad_out) CHK(hipMemcpyAsync(grad_out, C->grad, NP * sizeof(float), hipMemcpyDeviceToHost, s));
     if (apply) {
         C->step++;
         const float b1 = 0.9f, b2 = 0.999f;
         const float c1 = 1.0f - std::pow(b1, (float)C->step), c2 = 1.0f - std::pow(b2, (float)C->step);
-        hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, C->master, C->m, C->v, C->grad,
-                           NPARAM, (float)lr, b1, b2, 1e-8f, c1, c2);
+        hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, s, C->master, C->m, C->v, C->grad, NP,
+                           (float)lr, b1, b2, 1e-8f, c1, c2);
         CHK(hipGetLastError());
         CHK(cnn_pack(C, s));
     }

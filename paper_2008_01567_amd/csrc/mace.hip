@@ -6,11 +6,14 @@
 //
 // L~ is msf_prox_solve on W_0 started from the previous X_0: to the tolerance
 // (full proximal map) or for a fixed number of CG steps (the partial update
-// the paper uses with three coordinate-descent sweeps).  The paper's 2.5D CNN
-// denoisers are not available; the prior agents here are stand-ins that are
-// true proximal maps: symmetric plane-wise Gaussian smoothers in the xy, yz
-// and zx planes (eigenvalues in (0, 1]), or the ridge shrinkage
-// x / (1 + lambda sigma^2), the proximal map of (lambda/2) ||x||^2.
+// the paper uses with three coordinate-descent sweeps).  The prior agents are
+// the paper's multi-slice fusion denoisers H_xy,t, H_yz,t, H_zx,t (Sec. IV):
+// one trained 2.5D CNN (cnn.hip) applied to every 2D slice of the xy, yz or
+// zx planes with the same slice at time points t-2 .. t+2 as its channels;
+// or stand-ins that are true proximal maps, for which the equilibrium has a
+// closed form: symmetric plane-wise Gaussian smoothers in the xy, yz and zx
+// planes (eigenvalues in (0, 1]), or the ridge shrinkage x / (1 + lambda
+// sigma^2), the proximal map of (lambda/2) ||x||^2.
 //
 // Volumes are kept in the public layout [frame][nz][ny][nx].  The averaging
 // and the Mann update are one fused pass over the 2 (K + 1) state volumes.
@@ -111,6 +114,7 @@ void msf_mace_opts_default(msf_mace_opts *o)
     o->prior_param = 1.0;
     o->tol = 1e-6;
     o->cnn = nullptr;
+    o->prior_cnn = nullptr;
 }
 
 msf_status msf_mace_run(msf_plan *P, const float *x_init, const float *y, const float *lam, double sigma,
@@ -121,19 +125,24 @@ msf_status msf_mace_run(msf_plan *P, const float *x_init, const float *y, const 
     if (!P || !y || !lam || !x_out || !opts) { set_error("null argument"); return MSF_EINVAL; }
     const msf_mace_opts &o = *opts;
     if (!(sigma > 0.0 && std::isfinite(sigma)) || o.n_iter < 0 || !(o.beta > 0.0) || !(o.rho > 0.0 && o.rho < 1.0) ||
-        !(o.prior_param > 0.0) || o.partial_iters < 0 || (o.prior != MSF_PRIOR_PLANE_GAUSS && o.prior != MSF_PRIOR_RIDGE)) {
-        set_error("invalid MACE options (sigma > 0, n_iter >= 0, beta > 0, 0 < rho < 1, prior_param > 0)");
+        !(o.prior_param > 0.0) || o.partial_iters < 0 ||
+        (o.prior != MSF_PRIOR_PLANE_GAUSS && o.prior != MSF_PRIOR_RIDGE && o.prior != MSF_PRIOR_CNN) ||
+        (o.prior == MSF_PRIOR_CNN && (!o.prior_cnn || cnn_kind(o.prior_cnn) != MSF_CNN_DENOISER))) {
+        set_error("invalid MACE options (sigma > 0, n_iter >= 0, beta > 0, 0 < rho < 1, prior_param > 0, "
+                  "a known prior, a denoiser network for MSF_PRIOR_CNN)");
         return MSF_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
     const int K = 3;
     const int64_t n = P->nvox_total;
     std::vector<float *> W(K + 1, nullptr), X(K + 1, nullptr);
-    float *tmp = nullptr;
+    float *tmp = nullptr, *sa = nullptr, *sb = nullptr;
     auto cleanup = [&]() {
         for (float *q : W) if (q) (void)hipFree(q);
         for (float *q : X) if (q) (void)hipFree(q);
         if (tmp) (void)hipFree(tmp);
+        if (sa) (void)hipFree(sa);
+        if (sb) (void)hipFree(sb);
     };
     hipError_t e = hipSuccess;
     for (int k = 0; k <= K && e == hipSuccess; ++k) {
@@ -141,6 +150,10 @@ msf_status msf_mace_run(msf_plan *P, const float *x_init, const float *y, const 
         if (e == hipSuccess) e = hipMalloc((void **)&X[k], sizeof(float) * std::max<int64_t>(n, 1));
     }
     if (e == hipSuccess) e = hipMalloc((void **)&tmp, sizeof(float) * std::max<int64_t>(n, 1));
+    if (e == hipSuccess && o.prior == MSF_PRIOR_CNN) {   // plane sequences of the yz and zx agents
+        e = hipMalloc((void **)&sa, sizeof(float) * std::max<int64_t>(n, 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&sb, sizeof(float) * std::max<int64_t>(n, 1));
+    }
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "MACE state allocation"); }
     // X = W = [x_init; ...] (zero when x_init is NULL, the paper's initial condition)
     for (int k = 0; k <= K && e == hipSuccess; ++k) {
@@ -188,6 +201,13 @@ msf_status msf_mace_run(msf_plan *P, const float *x_init, const float *y, const 
         }
         // prior agents
         for (int k = 1; k <= K; ++k) {
+            if (o.prior == MSF_PRIOR_CNN) {
+                // H_k: the 2.5D denoiser on the slices of plane k (Sec. IV)
+                e = denoise25_internal(const_cast<msf_cnn *>(o.prior_cnn), W[k], P->nf, P->nz, P->ny, P->nx, k, X[k],
+                                       sa, sb, s);
+                if (e != hipSuccess) { cleanup(); return hip_fail(e, "CNN prior agent"); }
+                continue;
+            }
             if (o.prior == MSF_PRIOR_RIDGE) {
                 hipLaunchKernelGGL(k_scale, dim3(grid_n(n)), dim3(256), 0, s, W[k], X[k], n,
                                    (float)(1.0 / (1.0 + o.prior_param * sigma * sigma)));

@@ -234,3 +234,9 @@ hipError_t launch_vol_select(msf_plan &P, hipStream_t s);
 // network evaluation (cnn.hip): x0 = v + c f(v / c, g / c) on public-layout volumes
 hipError_t cnn_infer_internal(struct msf_cnn *C, const float *v, const float *g, int N, int Z, int Y, int X, float *x0,
                               hipStream_t s);
+// MSF_CNN_WARM_START or MSF_CNN_DENOISER
+int cnn_kind(const struct msf_cnn *C);
+// the 2.5D denoiser in plane 1 (xy), 2 (yz) or 3 (zx) of a [T][Z][Y][X]
+// sequence; out must not overlap w; planes 2 and 3 use two scratch volumes
+hipError_t denoise25_internal(struct msf_cnn *C, const float *w, int T, int Z, int Y, int X, int plane, float *out,
+                              float *scratch_a, float *scratch_b, hipStream_t s);

@@ -60,7 +60,7 @@ class msf_solve_stats(C.Structure):
 class msf_mace_opts(C.Structure):
     _fields_ = [("n_iter", C.c_int32), ("prior", C.c_int32), ("partial_iters", C.c_int32), ("max_iter", C.c_int32),
                 ("beta", C.c_double), ("rho", C.c_double), ("prior_param", C.c_double), ("tol", C.c_double),
-                ("cnn", C.c_void_p)]
+                ("cnn", C.c_void_p), ("prior_cnn", C.c_void_p)]
 
 
 class msf_mace_stats(C.Structure):
@@ -68,7 +68,7 @@ class msf_mace_stats(C.Structure):
                 ("cg_total", C.c_int64), ("seconds", C.c_double)]
 
 
-MSF_PRIOR_PLANE_GAUSS, MSF_PRIOR_RIDGE = 0, 1
+MSF_PRIOR_PLANE_GAUSS, MSF_PRIOR_RIDGE, MSF_PRIOR_CNN = 0, 1, 2
 
 
 class msf_timing(C.Structure):
@@ -84,7 +84,7 @@ EXPORTS = ["msf_solve_opts_default", "msf_plan_create", "msf_plan_destroy", "msf
            "msf_last_error", "msf_version", "msf_plan_set_timing", "msf_plan_get_timing",
            "msf_count_intersections", "msf_prox_features", "msf_cnn_create", "msf_cnn_destroy",
            "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step", "msf_mace_opts_default", "msf_mace_run", "msf_plan_autotune",
-           "msf_fixture_correct"]
+           "msf_fixture_correct", "msf_cnn_create_denoiser", "msf_cnn_kind", "msf_cnn_n_params", "msf_denoise25"]
 
 
 def lib():
@@ -117,14 +117,19 @@ def lib():
         L.msf_mace_run.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(msf_mace_opts), vp,
                                    C.POINTER(msf_mace_stats), vp]
         L.msf_cnn_create.argtypes = [C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_float), C.POINTER(vp)]
+        L.msf_cnn_create_denoiser.argtypes = [C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_float), C.POINTER(vp)]
         L.msf_cnn_destroy.argtypes = [vp]
+        L.msf_cnn_kind.argtypes = [vp]
+        L.msf_cnn_n_params.argtypes = [vp]
+        L.msf_cnn_n_params.restype = C.c_int64
+        L.msf_denoise25.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp]
         L.msf_cnn_get_params.argtypes = [vp, C.POINTER(C.c_float)]
         L.msf_cnn_infer.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp]
         L.msf_cnn_train_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                          C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_float), vp]
         for name in EXPORTS:
             if name not in ("msf_last_error", "msf_version", "msf_plan_destroy", "msf_solve_opts_default",
-                            "msf_cnn_destroy", "msf_mace_opts_default"):
+                            "msf_cnn_destroy", "msf_mace_opts_default", "msf_cnn_n_params"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -255,7 +260,7 @@ class Plan:
         return out
 
     def mace(self, y, lam, sigma, x_init=None, n_iter=10, prior=MSF_PRIOR_PLANE_GAUSS, prior_param=1.0, beta=1.0,
-             rho=0.5, partial_iters=0, tol=1e-6, max_iter=2000, cnn=None, out=None, stream=None):
+             rho=0.5, partial_iters=0, tol=1e-6, max_iter=2000, cnn=None, prior_cnn=None, out=None, stream=None):
         """Algorithm 1 (msf_mace_run); returns (X_0, stats)."""
         import torch
         if out is None:
@@ -265,6 +270,7 @@ class Plan:
         o.n_iter, o.prior, o.partial_iters, o.max_iter = int(n_iter), int(prior), int(partial_iters), int(max_iter)
         o.beta, o.rho, o.prior_param, o.tol = float(beta), float(rho), float(prior_param), float(tol)
         o.cnn = cnn._h.value if cnn is not None else None
+        o.prior_cnn = prior_cnn._h.value if prior_cnn is not None else None
         it = np.zeros(max(n_iter, 1), dtype=np.int64)
         st = msf_mace_stats(it.ctypes.data_as(C.POINTER(C.c_int64)), len(it), 0, 0, 0.0)
         xi = _ptr(x_init, self.n_vox) if x_init is not None else None
@@ -357,3 +363,60 @@ class Cnn:
         _check(lib().msf_cnn_train_step(self._h, _ptr(v), _ptr(g, v.numel()), _ptr(target, v.numel()), n, nz, ny, nx,
                                         float(lr), int(bool(apply)), C.byref(loss), gp, _stream(stream)))
         return loss.value, grad
+
+
+N_DENOISER_PARAMS = 5521
+
+
+class Denoiser(Cnn):
+    """The 2.5D denoiser of the multi-slice fusion prior agents (paper Sec. IV;
+    msf_cnn_create_denoiser).  params: FP32 [5521] (per layer W[out][in][3][3]
+    then b[out]); scales: (c_in, c_o)."""
+
+    def __init__(self, params, scales):
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        sc = np.asarray(scales, dtype=np.float32).reshape(-1)
+        if sc.size != 2:
+            raise ValueError("scales must be (c_in, c_o)")
+        h = C.c_void_p()
+        _check(lib().msf_cnn_create_denoiser(p.ctypes.data_as(C.POINTER(C.c_float)), p.size,
+                                             sc.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
+        self._h = h
+        self.scales = tuple(float(x) for x in sc)
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(N_DENOISER_PARAMS, dtype=np.float32)
+        _check(lib().msf_cnn_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def infer(self, stack, out=None, stream=None):
+        """stack [n][5][h][w] (time points t-2 .. t+2) -> denoised centre slices [n][h][w]."""
+        import torch
+        n, c, h, w = stack.shape
+        if c != 5:
+            raise ValueError("expected 5 time points per image")
+        if out is None:
+            out = torch.empty((n, h, w), dtype=stack.dtype, device=stack.device)
+        _check(lib().msf_cnn_infer(self._h, _ptr(stack), None, n, 1, h, w, _ptr(out, n * h * w), _stream(stream)))
+        return out
+
+    def train_step(self, stack, target, lr=1e-3, apply=True, want_grad=False, stream=None):
+        n, c, h, w = stack.shape
+        if c != 5:
+            raise ValueError("expected 5 time points per image")
+        loss = C.c_double()
+        grad = np.zeros(N_DENOISER_PARAMS, dtype=np.float32) if want_grad else None
+        gp = grad.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
+        _check(lib().msf_cnn_train_step(self._h, _ptr(stack), None, _ptr(target, n * h * w), n, 1, h, w, float(lr),
+                                        int(bool(apply)), C.byref(loss), gp, _stream(stream)))
+        return loss.value, grad
+
+    def agent(self, w, plane, out=None, stream=None):
+        """H_xy,t (plane 1), H_yz,t (2) or H_zx,t (3) on a [T][nz][ny][nx] volume (msf_denoise25)."""
+        import torch
+        T, nz, ny, nx = w.shape
+        if out is None:
+            out = torch.empty_like(w)
+        _check(lib().msf_denoise25(self._h, _ptr(w), T, nz, ny, nx, int(plane), _ptr(out, w.numel()),
+                                   _stream(stream)))
+        return out

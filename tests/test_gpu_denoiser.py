@@ -1,0 +1,200 @@
+"""GPU parity of the 2.5D denoiser of the multi-slice fusion prior agents
+(paper Sec. IV) against the FP64 oracle (same BF16 rounding points): the
+network on stacked slices, its parameter gradients, the agents H_xy,t,
+H_yz,t, H_zx,t on 4D volumes (ragged sizes, and sampled slices at the
+128^3 x 16 benchmark size), and MACE with these agents."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn as ocnn
+from oracle import mace
+from _problems import problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SCALES = (0.05, 0.005)
+
+
+@pytest.fixture(scope="module")
+def msf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_01567_amd import msf as m
+    m.lib()
+    return m
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _params(seed, last=1.0):
+    """Random 3x3 weights and biases, FP32-representable (the GPU's master copy)."""
+    rng = np.random.default_rng(seed)
+    ps = []
+    for li in range(4):
+        ci, co = ocnn.DENOISER_CHANNELS[li], ocnn.DENOISER_CHANNELS[li + 1]
+        w = rng.standard_normal((co, ci, 3, 3)) * np.sqrt(2.0 / (9 * ci)) * (last if li == 3 else 1.0)
+        ps.append((w.astype(np.float32).astype(np.float64),
+                   (rng.standard_normal(co) * 0.1).astype(np.float32).astype(np.float64)))
+    return ps
+
+
+def _volume(seed, shape):
+    rng = np.random.default_rng(seed)
+    return (0.03 + 0.01 * rng.standard_normal(shape)).astype(np.float32)
+
+
+def test_denoiser_forward_matches_oracle(msf):
+    params = _params(0)
+    rng = np.random.default_rng(1)
+    stack = (0.03 + 0.01 * rng.standard_normal((3, 5, 13, 37))).astype(np.float32)   # ragged x: 37 = 2 * 16 + 5
+    net = msf.Denoiser(ocnn.flatten(params), SCALES)
+    got = net.infer(_dev(stack)).cpu().numpy()
+    want, _ = ocnn.den_forward(params, stack.astype(np.float64), bf16=True, scale=SCALES)
+    c = stack[:, 2].astype(np.float64)
+    err = rel_l2(got - c, want - c)
+    print("denoiser forward: residual rel err %.2e" % err, flush=True)
+    assert err <= 3e-3
+    assert np.array_equal(net.params(), ocnn.flatten(params).astype(np.float32))
+
+
+def test_denoiser_gradients_match_oracle(msf):
+    params = _params(2)
+    rng = np.random.default_rng(3)
+    stack = (0.03 + 0.01 * rng.standard_normal((4, 5, 11, 21))).astype(np.float32)
+    tgt = (stack[:, 2] + 0.003 * rng.standard_normal((4, 11, 21))).astype(np.float32)
+    net = msf.Denoiser(ocnn.flatten(params), SCALES)
+    loss, grad = net.train_step(_dev(stack), _dev(tgt), lr=0.0, apply=False, want_grad=True)
+    out, cache = ocnn.den_forward(params, stack.astype(np.float64), bf16=True, scale=SCALES)
+    oloss, dx = ocnn.mse(out, tgt.astype(np.float64))
+    ograd = ocnn.flatten(ocnn.den_backward(params, cache, dx))
+    assert grad.size == ograd.size == 5521
+    assert abs(loss - oloss) <= 1e-3 * oloss
+    o = 0
+    for li in range(4):
+        ci, co = ocnn.DENOISER_CHANNELS[li], ocnn.DENOISER_CHANNELS[li + 1]
+        n = co * ci * 9 + co
+        err = rel_l2(grad[o:o + n], ograd[o:o + n])
+        print("denoiser layer", li, "grad rel err %.2e" % err, flush=True)
+        assert err <= 1e-2
+        o += n
+
+
+def test_denoiser_training_lowers_the_loss(msf):
+    """60 Adam steps on one batch whose noise variance is 2.5e-5: the loss falls
+    (the update has the gradient's sign)."""
+    rng = np.random.default_rng(4)
+    clean = (0.03 + 0.01 * rng.standard_normal((8, 1, 16, 24))).repeat(5, axis=1)
+    stack = (clean + 0.005 * rng.standard_normal(clean.shape)).astype(np.float32)
+    tgt = clean[:, 2].astype(np.float32)
+    net = msf.Denoiser(ocnn.flatten(_params(5, last=0.1)), SCALES)
+    losses = [net.train_step(_dev(stack), _dev(tgt), lr=2e-3)[0] for _ in range(60)]
+    print("losses", losses[0], losses[-1], flush=True)
+    assert np.isfinite(losses).all() and losses[-1] < 0.8 * losses[0]
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 10, 21), (3, 17, 6, 33), (1, 4, 18, 5)])
+def test_agents_match_oracle(msf, shape):
+    """H_k(W) for k = 1, 2, 3 on ragged 4D volumes (T = 1 and 3 clamp every
+    time neighbour), against the oracle's slice-by-slice agent."""
+    print("shape", shape, flush=True)
+    params = _params(6, last=0.5)
+    net = msf.Denoiser(ocnn.flatten(params), SCALES)
+    W = _volume(7, shape)
+    Wd = _dev(W)
+    for k in (1, 2, 3):
+        got = net.agent(Wd, k).cpu().numpy()
+        want = mace.cnn_agent(W.astype(np.float64), k, params, SCALES)
+        err = rel_l2(got - W, want - W)
+        print("plane %d: residual rel err %.2e" % (k, err), flush=True)
+        assert err <= 3e-3
+    assert torch.equal(Wd, _dev(W))          # input untouched
+
+
+def test_agents_fullsize_sampled(msf):
+    """128^3 x 16 (the benchmark volume): each agent over the whole 4D volume,
+    checked on sampled slices of every plane, near both ends of the time axis
+    and in the middle (the oracle evaluates the same slices on their own)."""
+    from paper_2008_01567_amd import synth
+    cfg = synth.config("c2")
+    W = synth.make_phantom(cfg, dtype=np.float32)
+    W = W + np.random.default_rng(8).standard_normal(W.shape).astype(np.float32) * 0.004
+    params = _params(9, last=0.5)
+    net = msf.Denoiser(ocnn.flatten(params), SCALES)
+    Wd = _dev(W)
+    T = W.shape[0]
+    for k in (1, 2, 3):
+        out = net.agent(Wd, k)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        S = mace.to_slices(W, k)
+        G = mace.to_slices(got, k)
+        for t, s in ((0, 5), (1, 64), (T // 2, 100), (T - 1, 127)):
+            st = np.stack([S[min(max(t + d, 0), T - 1), s] for d in (-2, -1, 0, 1, 2)])[None].astype(np.float64)
+            want, _ = ocnn.den_forward(params, st, bf16=True, scale=SCALES)
+            err = rel_l2(G[t, s] - S[t, s], want[0] - S[t, s])
+            assert err <= 3e-3, (k, t, s, err)
+
+
+def test_agent_invalid_arguments(msf):
+    net = msf.Denoiser(ocnn.flatten(_params(10)), SCALES)
+    W = _dev(_volume(11, (2, 3, 4, 5)))
+    for plane in (0, 4):
+        with pytest.raises(msf.MsfError):
+            net.agent(W, plane)
+    with pytest.raises(msf.MsfError):
+        net.agent(W, 1, out=W)                                   # out overlaps w
+    with pytest.raises(msf.MsfError):                            # the denoiser takes 2D images
+        msf._check(msf.lib().msf_cnn_infer(net._h, msf._ptr(W), None, 2, 3, 4, 5, msf._ptr(torch.empty_like(W)),
+                                           msf._stream(None)))
+    warm = msf.Cnn(ocnn.flatten(ocnn.init_params(0)), 0.05)
+    with pytest.raises(msf.MsfError):                            # a warm-start network is no denoiser
+        msf._check(msf.lib().msf_denoise25(warm._h, msf._ptr(W), 2, 3, 4, 5, 1, msf._ptr(torch.empty_like(W)),
+                                           msf._stream(None)))
+    with pytest.raises(msf.MsfError):
+        msf.Denoiser(np.zeros(5520, dtype=np.float32), SCALES)
+    assert msf.lib().msf_cnn_kind(net._h) == 1 and msf.lib().msf_cnn_n_params(net._h) == 5521
+
+
+def test_mace_with_cnn_agents_matches_oracle(msf):
+    """Algorithm 1 with the three 2.5D denoiser agents: 4 Mann iterations, full
+    prox solves, GPU vs the oracle's Algorithm 1 with its own agents."""
+    cfg, g, x0, v, y, lam = problem("c1")
+    sigma, beta, rho, n_iter = cfg.sigma, 1.0, 0.5, 4
+    params = _params(12, last=0.3)
+    net = msf.Denoiser(ocnn.flatten(params), SCALES)
+    plan = msf.Plan(g)
+    xi = x0.astype(np.float32)
+    x, st = plan.mace(_dev(y), _dev(lam), sigma, x_init=_dev(xi), n_iter=n_iter, prior=msf.MSF_PRIOR_CNN,
+                      prior_cnn=net, beta=beta, rho=rho, tol=1e-9, max_iter=6000)
+    mats = [oracle.FrameMatrix(g, f) for f in range(g.n_frames)]
+
+    def agents(W, X):
+        x0s = []
+        for f, M in enumerate(mats):
+            s = g.sino_slice(f)
+            xf, _ = M.prox_cg(W[0][f], y[s], lam[s], sigma, tol=1e-12, max_iter=20000, x0=X[0][f])
+            x0s.append(xf.reshape(W[0][f].shape))
+        return [np.stack(x0s)] + [mace.cnn_agent(W[k], k, params, SCALES) for k in (1, 2, 3)]
+    agents.n_agents = 4
+    want, _, _ = mace.mann_partial(agents, xi.astype(np.float64), beta, rho, n_iter)
+    err = rel_l2(x.cpu().numpy(), want)
+    print("MACE with CNN agents, %d iterations: rel err %.2e" % (n_iter, err), flush=True)
+    assert err <= 1e-3
+    with pytest.raises(msf.MsfError):            # MSF_PRIOR_CNN needs a denoiser network
+        plan.mace(_dev(y), _dev(lam), sigma, n_iter=1, prior=msf.MSF_PRIOR_CNN)
+    warm = msf.Cnn(ocnn.flatten(ocnn.init_params(0)), 0.05)
+    with pytest.raises(msf.MsfError):
+        plan.mace(_dev(y), _dev(lam), sigma, n_iter=1, prior=msf.MSF_PRIOR_CNN, prior_cnn=warm)
+
+
+def test_training_driver_end_to_end(msf, tmp_path):
+    from paper_2008_01567_amd import train_denoiser
+    out = tmp_path / "den.npz"
+    assert train_denoiser.main(["--volumes", "2", "--eval", "1", "--steps", "40", "--out", str(out)]) == 0
+    params, scales, meta = train_denoiser.load(str(out))
+    assert params.shape == (5521,) and np.isfinite(params).all() and np.allclose(scales, SCALES, rtol=1e-7)
+    assert meta["final_loss"] < meta["first_loss"]

@@ -143,3 +143,59 @@ def test_bf16_rounding():
     t = torch.tensor(vals, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(r, t)
     assert cnn.n_params() == 15169
+
+
+# ---- the 2.5D denoiser (five time points as channels, 3x3 kernels)
+
+def _den_params(seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for li in range(4):
+        ci, co = cnn.DENOISER_CHANNELS[li], cnn.DENOISER_CHANNELS[li + 1]
+        out.append((rng.standard_normal((co, ci, 3, 3)) / np.sqrt(ci * 9) * 1.5, rng.standard_normal(co) * 0.05))
+    return out
+
+
+def _torch_denoiser(params, stack, c_in, c_o):
+    """The denoiser with torch's conv2d (float64): x = s_2 + c_o f(stack / c_in)."""
+    tp = [(torch.tensor(w, requires_grad=True), torch.tensor(b, requires_grad=True)) for w, b in params]
+    h = torch.from_numpy(stack) / c_in
+    for li, (w, b) in enumerate(tp):
+        h = torch.nn.functional.conv2d(h, w, b, padding=1)
+        if li < 3:
+            h = torch.relu(h)
+    return torch.from_numpy(stack[:, 2]) + c_o * h[:, 0], tp
+
+
+def test_denoiser_matches_library_conv2d_and_autograd():
+    """The depth-1 embedding used for the 2D network equals torch's conv2d
+    network, values and parameter gradients (an independent implementation)."""
+    rng = np.random.default_rng(20)
+    params = _den_params(21)
+    stack = rng.standard_normal((3, 5, 7, 9))
+    target = rng.standard_normal((3, 7, 9))
+    c_in, c_o = 0.7, 0.3
+    x, cache = cnn.den_forward(params, stack, scale=(c_in, c_o))
+    loss, dx = cnn.mse(x, target)
+    grads = cnn.den_backward(params, cache, dx)
+    ref, tp = _torch_denoiser(params, stack, c_in, c_o)
+    assert np.allclose(x, ref.detach().numpy(), rtol=1e-12, atol=1e-12)
+    tl = ((ref - torch.from_numpy(target)) ** 2).mean()
+    tl.backward()
+    assert abs(tl.item() - loss) <= 1e-12 * abs(loss)
+    for (gw, gb), (w, b) in zip(grads, tp):
+        assert gw.shape == w.shape
+        assert np.allclose(gw, w.grad.numpy(), rtol=1e-10, atol=1e-12)
+        assert np.allclose(gb, b.grad.numpy(), rtol=1e-10, atol=1e-12)
+
+
+def test_denoiser_parameter_layout():
+    assert cnn.den_n_params() == 5521
+    p = _den_params(22)
+    vec = cnn.flatten(p)
+    assert vec.size == 5521
+    back = cnn.den_unflatten(vec)
+    assert all(np.array_equal(a, c) and np.array_equal(b, d) for (a, b), (c, d) in zip(p, back))
+    # W_1[o][i][ky][kx] sits at (o * 5 + i) * 9 + 3 ky + kx, then b_1 after 16 * 5 * 9 weights
+    assert vec[(3 * 5 + 4) * 9 + 3 * 2 + 1] == p[0][0][3, 4, 2, 1]
+    assert vec[16 * 5 * 9 + 7] == p[0][1][7]

@@ -67,53 +67,87 @@ def test_plane_smoothers_are_proximal_maps():
     assert abs(mace.plane_smoother(x, 1, 1.0)[0, 4, 4, 4] - 1.0) < 1e-14
 
 
-def test_slices_round_trip_and_neighbour_mean():
+def test_slices_round_trip_and_time_stack():
     rng = np.random.default_rng(3)
     W = rng.standard_normal((5, 3, 4, 6))
     for k in (1, 2, 3):
-        S = mace.to_slices(W, k)
-        assert np.array_equal(mace.from_slices(S, k, W.shape), W)
+        assert np.array_equal(mace.from_slices(mace.to_slices(W, k), k), W)
     # plane 2 images are (z, y) at fixed (t, x); plane 3 images are (z, x) at fixed (t, y)
-    S2 = mace.to_slices(W, 2).reshape(5, 6, 3, 4)
-    assert S2[1, 5, 2, 3] == W[1, 2, 3, 5]
-    S3 = mace.to_slices(W, 3).reshape(5, 4, 3, 6)
-    assert S3[4, 1, 0, 2] == W[4, 0, 1, 2]
-    m = mace.time_neighbour_mean(W)
-    assert np.allclose(m[2], (W[0] + W[1] + W[3] + W[4]) / 4)
-    assert np.allclose(m[0], (W[0] + W[0] + W[1] + W[2]) / 4)       # clamped at the ends
+    assert mace.to_slices(W, 2)[1, 5, 2, 3] == W[1, 2, 3, 5]
+    assert mace.to_slices(W, 3)[4, 1, 0, 2] == W[4, 0, 1, 2]
+    # channel c of slice (t, s) is the slice at time t + c - 2, clamped to [0, T)
+    T = W.shape[0]
+    st = mace.time_stack(W, 2).reshape(T, 6, 5, 3, 4)
+    for t in range(T):
+        for c in range(5):
+            tt = min(max(t + c - 2, 0), T - 1)
+            assert np.array_equal(st[t, 5, c], W[tt, :, :, 5])      # (z, y) image at x = 5
+    st1 = mace.time_stack(W, 1).reshape(T, 3, 5, 4, 6)
+    assert np.array_equal(st1[0, 1, 0], W[0, 1]) and np.array_equal(st1[0, 1, 4], W[2, 1])
+    assert np.array_equal(st1[4, 2, 3], W[4, 2]) and np.array_equal(st1[3, 2, 0], W[1, 2])
 
 
-def test_cnn_agent_with_identity_network():
-    """A network whose output is zero (last layer zero) is the identity agent; a
-    network that outputs its second input channel averages over time."""
+def _passthrough_params(last):
+    """Layers 1-3 copy input channel c < 5 into hidden channel c through the
+    centre tap (inputs are positive, so the ReLUs pass them); the last layer
+    outputs sum_c last[c] * channel c."""
+    from oracle import cnn
+    params = []
+    for li in range(4):
+        ci, co = cnn.DENOISER_CHANNELS[li], cnn.DENOISER_CHANNELS[li + 1]
+        w = np.zeros((co, ci, 3, 3))
+        if li < 3:
+            for c in range(5):
+                w[c, c, 1, 1] = 1.0
+        else:
+            w[0, :5, 1, 1] = last
+        params.append((w, np.zeros(co)))
+    return params
+
+
+def test_cnn_agent_with_zero_output_network_is_identity():
     from oracle import cnn
     rng = np.random.default_rng(4)
     W = rng.uniform(0, 1, (4, 3, 5, 6))
-    params = cnn.init_params(1)
+    params = cnn.den_init_params(1)
     params[3] = (np.zeros_like(params[3][0]), np.zeros_like(params[3][1]))
     for k in (1, 2, 3):
-        assert np.allclose(mace.cnn_agent(W, k, params, (1.0, 1.0, 1.0)), cnn.bf16_round(W) * 0 + W, atol=0)
+        assert np.array_equal(mace.cnn_agent(W, k, params, (1.0, 1.0)), W)
 
 
-def test_cnn_agent_centre_tap_network_closed_form():
-    """A network that only passes its two channels through the centre tap and
-    outputs alpha (channel 1 - channel 0) gives H(W) = W + alpha (mean_t W - W):
-    the time-neighbour channel and the residual output are wired as stated."""
-    from oracle import cnn
+def test_cnn_agent_time_filter_networks_closed_form():
+    """Centre-tap networks make H a filter along time alone, the same in every
+    plane: f = s_{t-2} - s_t gives H(W)_t = W_{clamp(t-2)} (the channel order),
+    and f = alpha (mean of the four neighbours - s_t) gives the closed-form
+    time smoothing; the scales enter as c_o / c_in."""
     rng = np.random.default_rng(5)
     W = rng.uniform(0.1, 1.0, (5, 3, 4, 6))
-    alpha = 0.25
-    params = []
-    for li, (ci, co) in enumerate(zip(cnn.CHANNELS[:-1], cnn.CHANNELS[1:])):
-        w = np.zeros((co, ci, 3, 3, 3))
-        if li < 3:
-            w[0, 0, 1, 1, 1] = 1.0
-            w[1, 1, 1, 1, 1] = 1.0
-        else:
-            w[0, 0, 1, 1, 1] = -alpha
-            w[0, 1, 1, 1, 1] = alpha
-        params.append((w, np.zeros(co)))
-    want = W + alpha * (mace.time_neighbour_mean(W) - W)
+    T = W.shape[0]
+    cl = lambda t: min(max(t, 0), T - 1)
+    shift = _passthrough_params(np.array([1.0, 0.0, -1.0, 0.0, 0.0]))
+    want = np.stack([W[cl(t - 2)] for t in range(T)])
     for k in (1, 2, 3):
-        got = mace.cnn_agent(W, k, params, (1.0, 1.0, 1.0))
-        assert np.allclose(got, want, rtol=0, atol=1e-2 * alpha), k     # inputs rounded to bf16
+        got = mace.cnn_agent(W, k, shift, (1.0, 1.0))
+        assert np.allclose(got, want, rtol=0, atol=2 * 2.0 ** -8), k      # inputs rounded to bf16
+    alpha, c_in, c_o = 0.25, 0.5, 2.0
+    smooth = _passthrough_params(alpha * np.array([0.25, 0.25, -1.0, 0.25, 0.25]))
+    want = np.stack([W[t] + (c_o / c_in) * alpha * (0.25 * (W[cl(t - 2)] + W[cl(t - 1)] + W[cl(t + 1)]
+                                                            + W[cl(t + 2)]) - W[t]) for t in range(T)])
+    for k in (1, 2, 3):
+        got = mace.cnn_agent(W, k, smooth, (c_in, c_o))
+        assert np.allclose(got, want, rtol=0, atol=2e-2 * alpha), k
+
+
+def test_cnn_agent_in_plane_kernel_orientation():
+    """A network that only reads the centre slice through the tap one row down
+    the image (kernel index (2, 1)) shifts every image of the plane by one row:
+    plane 1 rows are y, planes 2 and 3 rows are z (zero beyond the edge)."""
+    rng = np.random.default_rng(6)
+    W = rng.uniform(0.1, 1.0, (3, 4, 5, 6))
+    params = _passthrough_params(np.array([0.0, 0.0, -1.0, 0.0, 0.0]))
+    params[3][0][0, 2, 2, 1] = 1.0          # + the centre slice at row + 1
+    g1 = mace.cnn_agent(W, 1, params, (1.0, 1.0))
+    g2 = mace.cnn_agent(W, 2, params, (1.0, 1.0))
+    tol = 2 * 2.0 ** -8
+    assert np.allclose(g1[:, :, :-1], W[:, :, 1:], atol=tol) and np.allclose(g1[:, :, -1], 0.0, atol=tol)
+    assert np.allclose(g2[:, :-1], W[:, 1:], atol=tol) and np.allclose(g2[:, -1], 0.0, atol=tol)
