@@ -34,14 +34,14 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (two passes over one plain solve of the 128^3 x 16 workload,
-# launch shape 3,4,1,1), each scaled by what the same counter reads for the
+# launch shape 3,1,2,1), each scaled by what the same counter reads for the
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "cf8d3be72f3a014db5980e47702e916312d420f0528e705120a809d22d09db06",
+    "source_sha256": "d01157aa19d1d5e6b9036e375c6d923f2a659347ca4dbf82f52f38387312543b",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
-    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1251.8e6,
-    "read_bytes": 986.9e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.933,
+    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.1e6,
+    "read_bytes": 987.2e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.933,
     "profile": "profiles/gather_update_c2_128x16_counters.md",
 }
 

@@ -97,51 +97,80 @@ struct ConvArgs {
     float scale;            // EPI_RESID
 };
 
-template <int EPI>
+// one wave: 16 consecutive x voxels of one (n, z, y) row, all 16 output
+// channels, one MFMA per tap
+struct SegPos {
+    int n, z, y, x0;
+};
+
+__device__ __forceinline__ SegPos seg_pos(int64_t seg, int nsx, int Y, int Z)
+{
+    SegPos p;
+    int64_t t = seg;
+    p.x0 = (int)(t % nsx) * 16; t /= nsx;
+    p.y = (int)(t % Y); t /= Y;
+    p.z = (int)(t % Z);
+    p.n = (int)(t / Z);
+    return p;
+}
+
+// The NT = 9 NDZ tap inputs of a segment: lane (r, g) holds voxel x0 + r + dx
+// - 1, input channels 4g .. 4g + 3 (zero outside the volume).  NDZ = 1 reads
+// the depth-centre taps only (exact for depth-1 images).
+template <int NDZ>
+__device__ __forceinline__ void load_taps(const ConvArgs &A, const SegPos &p, int r, int g, v4s *a)
+{
+#pragma unroll
+    for (int t = 0; t < NDZ * 9; ++t) {
+        const int dz = NDZ == 1 ? 1 : t / 9, dy = (t / 3) % 3, dx = t % 3;
+        const int zz = p.z + dz - 1, yy = p.y + dy - 1, xx = p.x0 + r + dx - 1;
+        const bool ok = zz >= 0 && zz < A.Z && yy >= 0 && yy < A.Y && xx >= 0 && xx < A.X;
+        const int64_t vox = (((int64_t)p.n * A.Z + zz) * A.Y + yy) * A.X + xx;
+        a[t] = ok ? *reinterpret_cast<const v4s *>(A.in + vox * CH + 4 * g) : v4s{0, 0, 0, 0};
+    }
+}
+
+// All tap inputs of a segment are loaded before its MFMAs, and the next
+// segment's while the current one is multiplied (latency of the gathers
+// hidden behind a whole segment of work).
+template <int EPI, int NDZ>
 __global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
 {
-    __shared__ v4s wl[TAPS * CH * 4];   // [tap][out][k-group]: 4 input channels each
-    const v4s *wsrc = reinterpret_cast<const v4s *>(A.w);
-    for (int i = threadIdx.x; i < TAPS * CH * 4; i += blockDim.x) wl[i] = wsrc[i];
+    constexpr int NT = NDZ * 9;
+    constexpr int T0 = NDZ == 1 ? 9 : 0;                // first kernel tap used
+    __shared__ v4s wl[NT * CH * 4];   // [tap][out][k-group]: 4 input channels each
+    const v4s *wsrc = reinterpret_cast<const v4s *>(A.w) + T0 * CH * 4;
+    for (int i = threadIdx.x; i < NT * CH * 4; i += blockDim.x) wl[i] = wsrc[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int nsx = (A.X + 15) / 16;
     const int64_t nseg = (int64_t)A.N * A.Z * A.Y * nsx;
-    for (int64_t seg = (int64_t)blockIdx.x * 4 + wave; seg < nseg; seg += (int64_t)gridDim.x * 4) {
-        int64_t t = seg;
-        const int xs = (int)(t % nsx); t /= nsx;
-        const int y = (int)(t % A.Y); t /= A.Y;
-        const int z = (int)(t % A.Z);
-        const int n = (int)(t / A.Z);
-        const int x0 = xs * 16;
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        // z and y are the same for the whole wave: taps outside the volume
-        // (zero inputs) are skipped, so depth-1 images run the 9 in-plane taps
-        for (int dz = 0; dz < 3; ++dz) {
-            const int zz = z + dz - 1;
-            if (zz < 0 || zz >= A.Z) continue;
-            for (int dy = 0; dy < 3; ++dy) {
-                const int yy = y + dy - 1;
-                if (yy < 0 || yy >= A.Y) continue;
-                const int64_t row = (((int64_t)n * A.Z + zz) * A.Y + yy) * A.X;
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const int xx = x0 + r + dx - 1;
-                    v4s a = {0, 0, 0, 0};
-                    if (xx >= 0 && xx < A.X) a = *reinterpret_cast<const v4s *>(A.in + (row + xx) * CH + 4 * g);
-                    const v4s b = wl[((dz * 3 + dy) * 3 + dx) * (CH * 4) + r * 4 + g];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-                }
-            }
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    int64_t seg = (int64_t)blockIdx.x * 4 + wave;
+    if (seg >= nseg) return;
+    const float bias = A.bias ? A.bias[r] : 0.0f;
+    SegPos p = seg_pos(seg, nsx, A.Y, A.Z);
+    v4s cur[NT];
+    load_taps<NDZ>(A, p, r, g, cur);
+    for (; seg < nseg; seg += stride) {
+        const int64_t sn = seg + stride;
+        SegPos pn = p;
+        v4s nxt[NT];
+        if (sn < nseg) {
+            pn = seg_pos(sn, nsx, A.Y, A.Z);
+            load_taps<NDZ>(A, pn, r, g, nxt);
         }
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(cur[t], wl[t * (CH * 4) + r * 4 + g], acc, 0, 0, 0);
         // lane holds output voxel x0 + 4g + j, channel r
-        const float bias = A.bias ? A.bias[r] : 0.0f;
-        const int64_t vrow = (((int64_t)n * A.Z + z) * A.Y + y) * A.X;
-        const int64_t vbase = (int64_t)n * A.v_stride + A.v_off + ((int64_t)z * A.Y + y) * A.X;
+        const int64_t vrow = (((int64_t)p.n * A.Z + p.z) * A.Y + p.y) * A.X;
+        const int64_t vbase = (int64_t)p.n * A.v_stride + A.v_off + ((int64_t)p.z * A.Y + p.y) * A.X;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int xv = x0 + 4 * g + j;
+            const int xv = p.x0 + 4 * g + j;
             if (xv >= A.X) continue;
             const int64_t vox = vrow + xv;
             const float val = acc[j] + bias;
@@ -152,6 +181,11 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
             } else {
                 if (r == 0) A.out_f[vox] = A.v[vbase + xv] + A.scale * val;
             }
+        }
+        if (sn < nseg) {
+            p = pn;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
         }
     }
 }
@@ -294,19 +328,20 @@ __device__ __forceinline__ float pack_src(const PackIn &P, int64_t img, int64_t 
     return P.a[((int64_t)tt * P.S + si) * per + loc];
 }
 
+// one thread per voxel: its 16 channels (32 bytes) in two 16-byte stores
 __global__ void k_pack_input(const PackIn P, int64_t n, int64_t per, uint16_t *__restrict__ h0)
 {
     const int cin = P.mode == IN_WARM ? 2 : 5;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * CH; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t vox = e / CH;
-        const int c = (int)(e % CH);
-        uint16_t h = 0;
-        if (c < cin) {
-            const int64_t img = vox / per;
+    for (int64_t vox = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; vox < n; vox += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t img = vox / per, loc = vox - img * per;
+        uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < cin; ++c) {
             const float sc = (P.mode == IN_WARM && c == 1) ? P.inv1 : P.inv0;
-            h = f2bf(pack_src(P, img, vox - img * per, c, per) * sc);
+            w[c >> 1] |= (uint32_t)f2bf(pack_src(P, img, loc, c, per) * sc) << (16 * (c & 1));
         }
-        h0[e] = h;
+        uint4 *dst = reinterpret_cast<uint4 *>(h0 + vox * CH);
+        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
     }
 }
 
@@ -422,11 +457,22 @@ hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const flo
 {
     ConvArgs A{in, w, bias, N, Z, Y, X, out_bf, mask, out_f, v, v_stride, v_off, scale};
     const int64_t nseg = (int64_t)N * Z * Y * ((X + 15) / 16);
-    const dim3 grid(grid_of(nseg, 4)), block(256);
+    // about 8 segments per wave when there is enough work, at most 32 blocks per CU
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((nseg + 31) / 32, 8192))), block(256);
+    const bool flat = Z == 1;      // depth-1 images: only the depth-centre taps can be non-zero
     switch (epi) {
-    case EPI_RELU: hipLaunchKernelGGL(k_conv<EPI_RELU>, grid, block, 0, s, A); break;
-    case EPI_MASK: hipLaunchKernelGGL(k_conv<EPI_MASK>, grid, block, 0, s, A); break;
-    default: hipLaunchKernelGGL(k_conv<EPI_RESID>, grid, block, 0, s, A); break;
+    case EPI_RELU:
+        if (flat) hipLaunchKernelGGL((k_conv<EPI_RELU, 1>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_conv<EPI_RELU, 3>), grid, block, 0, s, A);
+        break;
+    case EPI_MASK:
+        if (flat) hipLaunchKernelGGL((k_conv<EPI_MASK, 1>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_conv<EPI_MASK, 3>), grid, block, 0, s, A);
+        break;
+    default:
+        if (flat) hipLaunchKernelGGL((k_conv<EPI_RESID, 1>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_conv<EPI_RESID, 3>), grid, block, 0, s, A);
+        break;
     }
     return hipGetLastError();
 }
@@ -438,7 +484,7 @@ hipError_t cnn_forward(msf_cnn *C, const PackIn &in, int N, int Z, int Y, int X,
 {
     const int64_t per = (int64_t)Z * Y * X, n = (int64_t)N * per;
     hipError_t e;
-    hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n * CH, 256)), dim3(256), 0, s, in, n, per, C->h[0]);
+    hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n, 256)), dim3(256), 0, s, in, n, per, C->h[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int l = 0; l < 3; ++l)
         if ((e = launch_conv(EPI_RELU, C->h[l], C->wf + l * WPACK, C->bias + l * CH, N, Z, Y, X, C->h[l + 1],
@@ -484,6 +530,53 @@ __global__ void k_plane_transpose(const float *__restrict__ in, float *__restric
         if (to) out[q] = in[i];
         else out[i] = in[q];
     }
+}
+
+// plane 2 with coalesced reads and writes: one 32 x 32 (y, x) tile of one
+// (t, z) slice per block, through LDS (256 threads = 32 x 8)
+__global__ __launch_bounds__(256) void k_transpose_p2(const float *__restrict__ in, float *__restrict__ out, int Z,
+                                                      int Y, int X, int to)
+{
+    __shared__ float tile[32][33];
+    const int tz = blockIdx.z, t = tz / Z, z = tz - t * Z;
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t vslice = (int64_t)tz * Y * X;                 // volume [t][z][.][.]
+    auto sidx = [&](int x, int y) { return (((int64_t)t * X + x) * Z + z) * Y + y; };   // sequence [t][x][z][y]
+    if (to) {
+        for (int k = ty; k < 32; k += 8) {
+            const int y = by + k, x = bx + tx;
+            if (y < Y && x < X) tile[k][tx] = in[vslice + (int64_t)y * X + x];
+        }
+        __syncthreads();
+        for (int k = ty; k < 32; k += 8) {
+            const int x = bx + k, y = by + tx;
+            if (y < Y && x < X) out[sidx(x, y)] = tile[tx][k];
+        }
+    } else {
+        for (int k = ty; k < 32; k += 8) {
+            const int x = bx + k, y = by + tx;
+            if (y < Y && x < X) tile[tx][k] = in[sidx(x, y)];
+        }
+        __syncthreads();
+        for (int k = ty; k < 32; k += 8) {
+            const int y = by + k, x = bx + tx;
+            if (y < Y && x < X) out[vslice + (int64_t)y * X + x] = tile[k][tx];
+        }
+    }
+}
+
+hipError_t plane_transpose(const float *in, float *out, int T, int Z, int Y, int X, int plane, int to, hipStream_t s)
+{
+    const int64_t slices = (int64_t)T * Z;
+    if (plane == 2 && slices <= 65535) {
+        const dim3 grid((unsigned)((X + 31) / 32), (unsigned)((Y + 31) / 32), (unsigned)slices);
+        hipLaunchKernelGGL(k_transpose_p2, grid, dim3(256), 0, s, in, out, Z, Y, X, to);
+    } else {
+        const int64_t n = slices * Y * X;
+        hipLaunchKernelGGL(k_plane_transpose, dim3(grid_of(n, 256)), dim3(256), 0, s, in, out, T, Z, Y, X, plane, to);
+    }
+    return hipGetLastError();
 }
 
 // the denoiser on a plane sequence [T][S][H][W] (images chunked so that the
@@ -621,15 +714,12 @@ hipError_t denoise25_internal(msf_cnn *C, const float *w, int T, int Z, int Y, i
                               float *scratch_a, float *scratch_b, hipStream_t s)
 {
     if (plane == 1) return denoise_sequence(C, w, T, Z, Y, X, out, s);
-    const int64_t n = (int64_t)T * Z * Y * X;
-    hipLaunchKernelGGL(k_plane_transpose, dim3(grid_of(n, 256)), dim3(256), 0, s, w, scratch_a, T, Z, Y, X, plane, 1);
-    hipError_t e = hipGetLastError();
+    hipError_t e = plane_transpose(w, scratch_a, T, Z, Y, X, plane, 1, s);
     if (e != hipSuccess) return e;
     e = plane == 2 ? denoise_sequence(C, scratch_a, T, X, Z, Y, scratch_b, s)
                    : denoise_sequence(C, scratch_a, T, Y, Z, X, scratch_b, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plane_transpose, dim3(grid_of(n, 256)), dim3(256), 0, s, scratch_b, out, T, Z, Y, X, plane, 0);
-    return hipGetLastError();
+    return plane_transpose(scratch_b, out, T, Z, Y, X, plane, 0, s);
 }
 
 extern "C" {
