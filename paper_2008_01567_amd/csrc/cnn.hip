@@ -84,6 +84,32 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Sources of the input channels of images [n0, n0 + n / per):
+//   IN_WARM:  channel 0 = a / c_v, channel 1 = g / c_g (volumes [img][per]);
+//   IN_STACK: channel c = a[img][c][per] / c_in, c < 5;
+//   IN_SEQ:   a is a sequence [T][S][per] of S images per time point; image
+//             t S + s has channel c = the same image at time clamp(t + c - 2)
+//             / c_in, c < 5 (time points t-2 .. t+2, repeated at the ends).
+enum InMode : int { IN_WARM = 0, IN_STACK = 1, IN_SEQ = 2 };
+
+struct PackIn {
+    int mode;
+    const float *a, *g;
+    int64_t n0;           // first image (IN_SEQ)
+    int T, S;             // IN_SEQ
+    float inv0, inv1;
+};
+
+__device__ __forceinline__ float pack_src(const PackIn &P, int64_t img, int64_t loc, int c, int64_t per)
+{
+    if (P.mode == IN_WARM) return c == 0 ? P.a[img * per + loc] : P.g[img * per + loc];
+    if (P.mode == IN_STACK) return P.a[(img * 5 + c) * per + loc];
+    const int64_t gi = P.n0 + img;
+    const int t = (int)(gi / P.S), si = (int)(gi - (int64_t)t * P.S);
+    const int tt = min(max(t + c - 2, 0), P.T - 1);
+    return P.a[((int64_t)tt * P.S + si) * per + loc];
+}
+
 struct ConvArgs {
     const uint16_t *in;     // [N][Z][Y][X][16] bf16
     const uint16_t *w;      // [27][16 out][16 in] bf16
@@ -95,7 +121,40 @@ struct ConvArgs {
     const float *v;         // EPI_RESID: residual base of image n at v + n * v_stride + v_off
     int64_t v_stride, v_off;
     float scale;            // EPI_RESID
+    PackIn pin;             // k_conv2d<.., true>: the FP32 sources of the first layer's input channels
 };
+
+// The MFMAs take the weights as the A operand and the activations as B, so
+// lane (r, g) ends with output channels 4g .. 4g + 3 of voxel r of its
+// segment: one 8-byte store per lane, 512 contiguous bytes per wave.
+template <int EPI>
+__device__ __forceinline__ void conv_store(const ConvArgs &A, const v4f &acc, const float4 &b, int64_t vox,
+                                           int64_t vres, int g)
+{
+    const float o[4] = {acc[0] + b.x, acc[1] + b.y, acc[2] + b.z, acc[3] + b.w};
+    if (EPI == EPI_RELU) {
+        uint2 w;
+        w.x = (uint32_t)f2bf(fmaxf(o[0], 0.0f)) | ((uint32_t)f2bf(fmaxf(o[1], 0.0f)) << 16);
+        w.y = (uint32_t)f2bf(fmaxf(o[2], 0.0f)) | ((uint32_t)f2bf(fmaxf(o[3], 0.0f)) << 16);
+        *reinterpret_cast<uint2 *>(A.out_bf + vox * CH + 4 * g) = w;
+    } else if (EPI == EPI_MASK) {
+        const uint2 m = *reinterpret_cast<const uint2 *>(A.mask + vox * CH + 4 * g);
+        const uint16_t mk[4] = {(uint16_t)(m.x & 0xFFFFu), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xFFFFu),
+                                (uint16_t)(m.y >> 16)};
+        uint16_t h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h[j] = bf2f(mk[j]) > 0.0f ? f2bf(o[j]) : (uint16_t)0;
+        *reinterpret_cast<uint2 *>(A.out_bf + vox * CH + 4 * g) =
+            make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+    } else {
+        if (g == 0) A.out_f[vox] = A.v[vres] + A.scale * o[0];
+    }
+}
+
+__device__ __forceinline__ float4 conv_bias(const ConvArgs &A, int g)
+{
+    return A.bias ? *reinterpret_cast<const float4 *>(A.bias + 4 * g) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
 
 // one wave: 16 consecutive x voxels of one (n, z, y) row, all 16 output
 // channels, one MFMA per tap
@@ -149,7 +208,7 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
     const int64_t stride = (int64_t)gridDim.x * 4;
     int64_t seg = (int64_t)blockIdx.x * 4 + wave;
     if (seg >= nseg) return;
-    const float bias = A.bias ? A.bias[r] : 0.0f;
+    const float4 bias = conv_bias(A, g);
     SegPos p = seg_pos(seg, nsx, A.Y, A.Z);
     v4s cur[NT];
     load_taps<NDZ>(A, p, r, g, cur);
@@ -164,28 +223,168 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
         v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(cur[t], wl[t * (CH * 4) + r * 4 + g], acc, 0, 0, 0);
-        // lane holds output voxel x0 + 4g + j, channel r
-        const int64_t vrow = (((int64_t)p.n * A.Z + p.z) * A.Y + p.y) * A.X;
-        const int64_t vbase = (int64_t)p.n * A.v_stride + A.v_off + ((int64_t)p.z * A.Y + p.y) * A.X;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int xv = p.x0 + 4 * g + j;
-            if (xv >= A.X) continue;
-            const int64_t vox = vrow + xv;
-            const float val = acc[j] + bias;
-            if (EPI == EPI_RELU) {
-                A.out_bf[vox * CH + r] = f2bf(fmaxf(val, 0.0f));
-            } else if (EPI == EPI_MASK) {
-                A.out_bf[vox * CH + r] = bf2f(A.mask[vox * CH + r]) > 0.0f ? f2bf(val) : (uint16_t)0;
-            } else {
-                if (r == 0) A.out_f[vox] = A.v[vbase + xv] + A.scale * val;
-            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[t * (CH * 4) + r * 4 + g], cur[t], acc, 0, 0, 0);
+        const int xv = p.x0 + r;
+        if (xv < A.X) {
+            const int64_t vox = (((int64_t)p.n * A.Z + p.z) * A.Y + p.y) * A.X + xv;
+            const int64_t vres = (int64_t)p.n * A.v_stride + A.v_off + ((int64_t)p.z * A.Y + p.y) * A.X + xv;
+            conv_store<EPI>(A, acc, bias, vox, vres, g);
         }
         if (sn < nseg) {
             p = pn;
 #pragma unroll
             for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
+        }
+    }
+}
+
+// Depth-1 images (the 2.5D denoiser): a workgroup owns a tile of TY rows x
+// 64 voxels of one image and stages its input rows plus a one-voxel halo in
+// LDS with 16-byte coalesced loads, so each input voxel is read from memory
+// about (TY + 2) / TY times instead of nine; wave w computes the 16-voxel
+// segment 16w .. 16w + 15 of every row of the tile from LDS.  The next
+// tile's rows are loaded into registers while the current one is multiplied.
+constexpr int TY = 8, TXW = 64, TROW = TXW + 2;
+constexpr int TILE_U4 = (TY + 2) * TROW * 2;          // 16-byte chunks in the staged rows
+constexpr int TILE_LD = (TILE_U4 + 255) / 256;        // per thread
+
+struct TilePos {
+    int n, y0, x0;
+};
+
+__device__ __forceinline__ TilePos tile_pos(int64_t t, int ntx, int nty)
+{
+    TilePos p;
+    p.x0 = (int)(t % ntx) * TXW;
+    t /= ntx;
+    p.y0 = (int)(t % nty) * TY;
+    p.n = (int)(t / nty);
+    return p;
+}
+
+__device__ __forceinline__ void tile_fetch(const ConvArgs &A, const TilePos &p, uint4 (&reg)[TILE_LD])
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(A.in);
+#pragma unroll
+    for (int k = 0; k < TILE_LD; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        const int row = idx / (2 * TROW), rem = idx - row * (2 * TROW);
+        const int gy = p.y0 - 1 + row, gx = p.x0 - 1 + (rem >> 1);
+        const bool ok = idx < TILE_U4 && gy >= 0 && gy < A.Y && gx >= 0 && gx < A.X;
+        reg[k] = ok ? src[(((int64_t)p.n * A.Y + gy) * A.X + gx) * 2 + (rem & 1)] : make_uint4(0, 0, 0, 0);
+    }
+}
+
+// First layer straight from the FP32 sources: each thread stages whole voxels
+// (its input channels scaled and rounded to BF16 as the input pack does).
+constexpr int TILE_VOX = (TY + 2) * TROW;
+constexpr int TILE_VLD = (TILE_VOX + 255) / 256;      // voxels per thread
+
+__device__ __forceinline__ void tile_fetch_f32(const ConvArgs &A, const TilePos &p, float (&reg)[TILE_VLD][5])
+{
+    // the tile's image is one image: its channel planes and scales are uniform
+    const PackIn &P = A.pin;
+    const int64_t per = (int64_t)A.Y * A.X;
+    const int cin = P.mode == IN_WARM ? 2 : 5;
+    const float *ch[5];
+    float sc[5];
+    if (P.mode == IN_SEQ) {
+        const int64_t gi = P.n0 + p.n;
+        const int t = (int)(gi / P.S), si = (int)(gi - (int64_t)t * P.S);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) ch[c] = P.a + ((int64_t)min(max(t + c - 2, 0), P.T - 1) * P.S + si) * per;
+    } else if (P.mode == IN_STACK) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) ch[c] = P.a + ((int64_t)p.n * 5 + c) * per;
+    } else {
+        ch[0] = P.a + (int64_t)p.n * per;
+        ch[1] = P.g + (int64_t)p.n * per;
+        ch[2] = ch[3] = ch[4] = ch[0];
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sc[c] = (P.mode == IN_WARM && c == 1) ? P.inv1 : P.inv0;
+#pragma unroll
+    for (int k = 0; k < TILE_VLD; ++k) {
+        const int vi = threadIdx.x + 256 * k;
+        const int row = vi / TROW, col = vi - row * TROW;
+        const int gy = p.y0 - 1 + row, gx = p.x0 - 1 + col;
+        const bool ok = vi < TILE_VOX && gy >= 0 && gy < A.Y && gx >= 0 && gx < A.X;
+        const int64_t loc = (int64_t)gy * A.X + gx;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) reg[k][c] = (ok && c < cin) ? ch[c][loc] * sc[c] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void tile_store_f32(uint4 *tile, const float (&reg)[TILE_VLD][5])
+{
+#pragma unroll
+    for (int k = 0; k < TILE_VLD; ++k) {
+        const int vi = threadIdx.x + 256 * k;
+        if (vi >= TILE_VOX) continue;
+        // f2bf(0) = 0, so the channels past the network's inputs stay zero
+        tile[2 * vi] = make_uint4((uint32_t)f2bf(reg[k][0]) | ((uint32_t)f2bf(reg[k][1]) << 16),
+                                  (uint32_t)f2bf(reg[k][2]) | ((uint32_t)f2bf(reg[k][3]) << 16),
+                                  (uint32_t)f2bf(reg[k][4]), 0u);
+        tile[2 * vi + 1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+template <int EPI, bool F32IN>
+__global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
+{
+    __shared__ v4s wl[9 * CH * 4];
+    __shared__ uint4 tile[TILE_U4];
+    const v4s *wsrc = reinterpret_cast<const v4s *>(A.w) + 9 * CH * 4;     // the depth-centre taps
+    for (int i = threadIdx.x; i < 9 * CH * 4; i += blockDim.x) wl[i] = wsrc[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int ntx = (A.X + TXW - 1) / TXW, nty = (A.Y + TY - 1) / TY;
+    const int64_t ntile = (int64_t)A.N * nty * ntx;
+    const float4 bias = conv_bias(A, g);
+    int64_t t = blockIdx.x;
+    if (t >= ntile) return;                  // the whole workgroup
+    TilePos p = tile_pos(t, ntx, nty);
+    uint4 reg[F32IN ? 1 : TILE_LD];
+    float regf[F32IN ? TILE_VLD : 1][5];
+    if constexpr (F32IN) tile_fetch_f32(A, p, regf);
+    else tile_fetch(A, p, reg);
+    const v4s *tl = reinterpret_cast<const v4s *>(tile);
+    for (; t < ntile; t += gridDim.x) {
+        __syncthreads();                     // the previous tile's reads are done
+        if constexpr (F32IN) {
+            tile_store_f32(tile, regf);
+        } else {
+#pragma unroll
+            for (int k = 0; k < TILE_LD; ++k) {
+                const int idx = threadIdx.x + 256 * k;
+                if (idx < TILE_U4) tile[idx] = reg[k];
+            }
+        }
+        __syncthreads();
+        const TilePos pc = p;
+        const int64_t tn = t + gridDim.x;
+        if (tn < ntile) {
+            p = tile_pos(tn, ntx, nty);
+            if constexpr (F32IN) tile_fetch_f32(A, p, regf);
+            else tile_fetch(A, p, reg);
+        }
+        const int xs = pc.x0 + 16 * wave;    // this wave's segment
+        if (xs >= A.X) continue;             // wave-uniform; no barrier until the next tile
+        for (int ry = 0; ry < TY && pc.y0 + ry < A.Y; ++ry) {
+            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    // staged voxel (row ry + dy, column 16 wave + r + dx), channels 4g .. 4g + 3
+                    const v4s a = tl[((ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[(dy * 3 + dx) * (CH * 4) + r * 4 + g], a, acc,
+                                                                    0, 0, 0);
+                }
+            const int y = pc.y0 + ry, xv = xs + r;
+            if (xv < A.X)
+                conv_store<EPI>(A, acc, bias, ((int64_t)pc.n * A.Y + y) * A.X + xv,
+                                (int64_t)pc.n * A.v_stride + A.v_off + (int64_t)y * A.X + xv, g);
         }
     }
 }
@@ -300,32 +499,6 @@ __global__ void k_pack(const float *__restrict__ master, const NetShape S, uint1
     const int fpt = net_ptap(S, TAPS - 1 - tap);
     wd[e] = (i < cout && o < cin && fpt >= 0) ? f2bf(W[(i * cin + o) * S.ptaps + fpt]) : (uint16_t)0;
     if (k < CH) bias[layer * CH + k] = k < cout ? master[S.poff[layer] + cout * cin * S.ptaps + k] : 0.0f;
-}
-
-// Sources of the input channels of images [n0, n0 + n / per):
-//   IN_WARM:  channel 0 = a / c_v, channel 1 = g / c_g (volumes [img][per]);
-//   IN_STACK: channel c = a[img][c][per] / c_in, c < 5;
-//   IN_SEQ:   a is a sequence [T][S][per] of S images per time point; image
-//             t S + s has channel c = the same image at time clamp(t + c - 2)
-//             / c_in, c < 5 (time points t-2 .. t+2, repeated at the ends).
-enum InMode : int { IN_WARM = 0, IN_STACK = 1, IN_SEQ = 2 };
-
-struct PackIn {
-    int mode;
-    const float *a, *g;
-    int64_t n0;           // first image (IN_SEQ)
-    int T, S;             // IN_SEQ
-    float inv0, inv1;
-};
-
-__device__ __forceinline__ float pack_src(const PackIn &P, int64_t img, int64_t loc, int c, int64_t per)
-{
-    if (P.mode == IN_WARM) return c == 0 ? P.a[img * per + loc] : P.g[img * per + loc];
-    if (P.mode == IN_STACK) return P.a[(img * 5 + c) * per + loc];
-    const int64_t gi = P.n0 + img;
-    const int t = (int)(gi / P.S), si = (int)(gi - (int64_t)t * P.S);
-    const int tt = min(max(t + c - 2, 0), P.T - 1);
-    return P.a[((int64_t)tt * P.S + si) * per + loc];
 }
 
 // one thread per voxel: its 16 channels (32 bytes) in two 16-byte stores
@@ -459,20 +632,21 @@ hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const flo
     const int64_t nseg = (int64_t)N * Z * Y * ((X + 15) / 16);
     // about 8 segments per wave when there is enough work, at most 32 blocks per CU
     const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((nseg + 31) / 32, 8192))), block(256);
-    const bool flat = Z == 1;      // depth-1 images: only the depth-centre taps can be non-zero
+    if (Z == 1) {
+        // depth-1 images: only the depth-centre taps can be non-zero; row tiles staged in LDS
+        const int64_t ntile = (int64_t)N * ((Y + TY - 1) / TY) * ((X + TXW - 1) / TXW);
+        const dim3 g2((unsigned)std::max<int64_t>(1, std::min<int64_t>(ntile, 4096)));
+        switch (epi) {
+        case EPI_RELU: hipLaunchKernelGGL((k_conv2d<EPI_RELU, false>), g2, block, 0, s, A); break;
+        case EPI_MASK: hipLaunchKernelGGL((k_conv2d<EPI_MASK, false>), g2, block, 0, s, A); break;
+        default: hipLaunchKernelGGL((k_conv2d<EPI_RESID, false>), g2, block, 0, s, A); break;
+        }
+        return hipGetLastError();
+    }
     switch (epi) {
-    case EPI_RELU:
-        if (flat) hipLaunchKernelGGL((k_conv<EPI_RELU, 1>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_conv<EPI_RELU, 3>), grid, block, 0, s, A);
-        break;
-    case EPI_MASK:
-        if (flat) hipLaunchKernelGGL((k_conv<EPI_MASK, 1>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_conv<EPI_MASK, 3>), grid, block, 0, s, A);
-        break;
-    default:
-        if (flat) hipLaunchKernelGGL((k_conv<EPI_RESID, 1>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_conv<EPI_RESID, 3>), grid, block, 0, s, A);
-        break;
+    case EPI_RELU: hipLaunchKernelGGL((k_conv<EPI_RELU, 3>), grid, block, 0, s, A); break;
+    case EPI_MASK: hipLaunchKernelGGL((k_conv<EPI_MASK, 3>), grid, block, 0, s, A); break;
+    default: hipLaunchKernelGGL((k_conv<EPI_RESID, 3>), grid, block, 0, s, A); break;
     }
     return hipGetLastError();
 }
@@ -480,13 +654,24 @@ hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const flo
 // Forward pass of N images [Z][Y][X] whose input channels come from `in`;
 // x0 = residual base + c_o f, the base of image n at vbase + n v_stride + v_off.
 hipError_t cnn_forward(msf_cnn *C, const PackIn &in, int N, int Z, int Y, int X, const float *vbase, int64_t v_stride,
-                       int64_t v_off, float *x0, hipStream_t s)
+                       int64_t v_off, float *x0, hipStream_t s, bool keep_input = false)
 {
     const int64_t per = (int64_t)Z * Y * X, n = (int64_t)N * per;
     hipError_t e;
-    hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n, 256)), dim3(256), 0, s, in, n, per, C->h[0]);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (int l = 0; l < 3; ++l)
+    int l0 = 0;
+    if (Z == 1 && !keep_input) {
+        // depth-1 inference: the first layer stages its input from the FP32 sources
+        ConvArgs A{nullptr, C->wf, C->bias, N, Z, Y, X, C->h[1], nullptr, nullptr, nullptr, 0, 0, 0.0f, in};
+        const int64_t ntile = (int64_t)N * ((Y + TY - 1) / TY) * ((X + TXW - 1) / TXW);
+        const dim3 g2((unsigned)std::max<int64_t>(1, std::min<int64_t>(ntile, 4096)));
+        hipLaunchKernelGGL((k_conv2d<EPI_RELU, true>), g2, dim3(256), 0, s, A);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        l0 = 1;
+    } else {
+        hipLaunchKernelGGL(k_pack_input, dim3(grid_of(n, 256)), dim3(256), 0, s, in, n, per, C->h[0]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (int l = l0; l < 3; ++l)
         if ((e = launch_conv(EPI_RELU, C->h[l], C->wf + l * WPACK, C->bias + l * CH, N, Z, Y, X, C->h[l + 1],
                              nullptr, nullptr, nullptr, 0, 0, 0.0f, s)) != hipSuccess)
             return e;
@@ -566,12 +751,30 @@ __global__ __launch_bounds__(256) void k_transpose_p2(const float *__restrict__ 
     }
 }
 
+// plane 3: vol [T][Z][Y][X] <-> seq [T][Y][Z][X], x rows stay contiguous:
+// one (t, z) slice per block, its Y rows copied as X-long runs
+__global__ __launch_bounds__(256) void k_transpose_p3(const float *__restrict__ in, float *__restrict__ out, int Z,
+                                                      int Y, int X, int to)
+{
+    const int tz = blockIdx.x, t = tz / Z, z = tz - t * Z;
+    const int n = Y * X;
+    const int64_t vslice = (int64_t)tz * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int y = i / X, x = i - y * X;
+        const int64_t is = (((int64_t)t * Y + y) * Z + z) * X + x;
+        if (to) out[is] = in[vslice + i];
+        else out[vslice + i] = in[is];
+    }
+}
+
 hipError_t plane_transpose(const float *in, float *out, int T, int Z, int Y, int X, int plane, int to, hipStream_t s)
 {
     const int64_t slices = (int64_t)T * Z;
     if (plane == 2 && slices <= 65535) {
         const dim3 grid((unsigned)((X + 31) / 32), (unsigned)((Y + 31) / 32), (unsigned)slices);
         hipLaunchKernelGGL(k_transpose_p2, grid, dim3(256), 0, s, in, out, Z, Y, X, to);
+    } else if (plane == 3 && (int64_t)Y * X < ((int64_t)1 << 31)) {
+        hipLaunchKernelGGL(k_transpose_p3, dim3((unsigned)slices), dim3(256), 0, s, in, out, Z, Y, X, to);
     } else {
         const int64_t n = slices * Y * X;
         hipLaunchKernelGGL(k_plane_transpose, dim3(grid_of(n, 256)), dim3(256), 0, s, in, out, T, Z, Y, X, plane, to);
@@ -813,7 +1016,7 @@ msf_status msf_cnn_train_step(msf_cnn *C, const float *v, const float *g, const 
     const bool stack = C->kind == MSF_CNN_DENOISER;
     CHK(cnn_reserve(C, nvox));
     CHK(cnn_forward(C, caller_input(C, v, g), n, nz, ny, nx, v, stack ? 5 * per : per, stack ? 2 * per : 0, C->pred,
-                    s));
+                    s, true));
     const unsigned lb = grid_of(nvox, 256);
     hipLaunchKernelGGL(k_mse, dim3(lb), dim3(256), 0, s, C->pred, target, nvox, C->co, C->ga, C->lpart);
     CHK(hipGetLastError());

@@ -21,6 +21,7 @@ import oracle
 from paper_2008_01567_amd import synth
 from paper_2008_01567_amd.calibration import FROZEN_TOL
 import _analytic
+from _problems import rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -150,3 +151,37 @@ def test_c5_mace_partial_updates(c5):
     assert np.abs(xh - v).max() > 0.0
     # Algorithm 1 itself (same kernels, same partial-update path) is checked against
     # the FP64 oracle on the reduced-size moving-object workload (test_gpu_mace.py)
+
+
+def test_c5_cnn_agents_sampled_and_fusion_run(c5):
+    """The 2.5D denoiser agents at full size (2.1e9 voxels per plane, evaluated in
+    chunks of 2^26 voxels): one slice of each plane against the oracle's denoiser
+    on that slice's five time points; then the workload's MACE run with the three
+    CNN agents (shipped weights): 10 outer iterations, 20-step partial updates."""
+    from oracle import cnn as ocnn
+    from oracle import mace as omace
+    from paper_2008_01567_amd import train_denoiser
+    msf, cfg, g, x0, v, y, lam, plan, dev = c5
+    params, scales, _ = train_denoiser.load()
+    net = msf.Denoiser(params, scales)
+    p64 = ocnn.den_unflatten(params)
+    T = g.n_frames
+    for k, (t, s) in zip((1, 2, 3), ((0, 130), (T // 2, 257), (T - 1, 40))):
+        out = net.agent(dev["v"], k)
+        torch.cuda.synchronize()
+        got = (out[t, s] if k == 1 else out[t, :, :, s] if k == 2 else out[t, :, s, :]).cpu().numpy()
+        del out
+        S = omace.to_slices(v, k)
+        st = np.stack([S[min(max(t + d, 0), T - 1), s] for d in (-2, -1, 0, 1, 2)])[None].astype(np.float64)
+        want, _ = ocnn.den_forward(p64, st, bf16=True, scale=scales)
+        centre = st[0, 2]
+        err = rel_l2(got - centre, want[0] - centre)
+        print("plane %d slice (t %d, %d): residual rel err %.2e" % (k, t, s, err), flush=True)
+        assert err <= 3e-3
+    x, st = plan.mace(dev["y"], dev["lam"], cfg.sigma, x_init=dev["v"], n_iter=10, partial_iters=20,
+                      prior=msf.MSF_PRIOR_CNN, prior_cnn=net)
+    print("multi-slice fusion, 10 iterations: %.1f s, cg per outer iteration %s" % (st["seconds"],
+                                                                               st["cg_iters"].tolist()), flush=True)
+    assert st["status"] == msf.MSF_OK
+    xh = x.cpu().numpy()
+    assert np.isfinite(xh).all() and np.abs(xh - v).max() > 0.0
