@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=6000)
     ap.add_argument("--check-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-agents", action="store_true", help="skip timing the 2.5D denoiser agents")
     ap.add_argument("--no-learned", action="store_true", help="time plain batched CG only")
     ap.add_argument("--cpu-iters", type=int, default=40, help="FP64 CG iterations timed in the CPU sample")
     ap.add_argument("--tiles", default="", help="rays_per_lane,waves_per_group,back_mode,xcd_remap (default: autotune)")
@@ -91,6 +92,33 @@ def cpu_baseline(cfg, geom, v_np, y_np, lam_np, gpu_iters, n_iter):
             "sample": "frame 0 of the same batch (%d^3 voxels x %d views, nnz %d): FP64 CSR build %.2fs + "
                       "%d FP64 CG iterations timed (%.3fs/iter), scaled to the %d iterations the GPU took on "
                       "that frame" % (geom.nx, g0.views_of(0), M.nnz, t_build, n_iter, per_iter, gpu_iters)}
+
+
+def time_agents(msf, torch, w, dev, reps=5):
+    """The three 2.5D denoiser agents (shipped weights) on the solved volume:
+    mean ms per call (HIP events on the current stream) and the fraction of
+    the HBM roofline for their algorithmic bytes (204 B per voxel in the xy
+    plane, 220 B with the two transposes of the yz and zx planes)."""
+    from paper_2008_01567_amd import train_denoiser
+    params, scales, _ = train_denoiser.load()
+    net = msf.Denoiser(params, scales)
+    out = torch.empty_like(w)
+    res = {}
+    for plane, name, bpv in ((1, "xy", 204.0), (2, "yz", 220.0), (3, "zx", 220.0)):
+        net.agent(w, plane, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            net.agent(w, plane, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = bpv * w.numel() / (ms * 1e-3) / 1e9
+        res[name] = {"ms": ms, "hbm_gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
+    res["bytes_per_voxel"] = {"xy": 204, "yz": 220, "zx": 220}
+    net.close()
+    return res
 
 
 def main():
@@ -220,6 +248,8 @@ def main():
                              "kernel or launch shape differs from the profiled one)",
                      "hbm_gbs_of_traffic": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9},
     }
+    if not args.no_agents:
+        result["denoiser_agents"] = time_agents(msf, torch, out, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, geom, v_np, y_np, lam_np, int(st_plain["iters"][0]),
                                               args.cpu_iters)

@@ -233,8 +233,11 @@ msf_status msf_cnn_train_step(msf_cnn *cnn, const float *v, const float *g, cons
  * fixed (t, z); (z, y) at fixed (t, x); (z, x) at fixed (t, y)) is replaced
  * by the denoiser's output with the same slice at t-2 .. t+2 as input, time
  * indices clamped to [0, n_frames).  cnn must be a MSF_CNN_DENOISER; out
- * (device, [n_frames][nz][ny][nx]) must not overlap w.  Planes 2 and 3
- * allocate two volumes of workspace for the call and synchronise. */
+ * (device, [n_frames][nz][ny][nx]) must not overlap w.  Asynchronous on
+ * stream.  Planes 2 and 3 use two volumes of workspace that the network keeps
+ * (allocated on first use and when a larger volume comes, freed by
+ * msf_cnn_destroy).  Calls with one network must not overlap in time: they
+ * share its activation and workspace buffers. */
 msf_status msf_denoise25(msf_cnn *cnn, const float *w, int32_t n_frames, int32_t nz, int32_t ny, int32_t nx,
                          int32_t plane, float *out, void *stream);
 

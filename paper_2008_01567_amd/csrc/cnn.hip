@@ -588,6 +588,9 @@ struct msf_cnn {
     // public-layout feature / prediction volumes used inside the solver
     float *io = nullptr;
     int64_t io_cap = 0;
+    // two plane sequences of msf_denoise25 (yz and zx planes)
+    float *seq = nullptr;
+    int64_t seq_cap = 0;
 };
 
 namespace {
@@ -942,7 +945,7 @@ void msf_cnn_destroy(msf_cnn *C)
     if (!C) return;
     (void)hipDeviceSynchronize();
     cnn_free_ws(C);
-    void *ps[] = {C->master, C->m, C->v, C->grad, C->wf, C->wd, C->bias, C->part, C->lpart, C->flag, C->io};
+    void *ps[] = {C->master, C->m, C->v, C->grad, C->wf, C->wd, C->bias, C->part, C->lpart, C->flag, C->io, C->seq};
     for (void *q : ps)
         if (q) (void)hipFree(q);
     if (C->hlpart) (void)hipHostFree(C->hlpart);
@@ -986,18 +989,21 @@ msf_status msf_denoise25(msf_cnn *C, const float *w, int32_t n_frames, int32_t n
     hipStream_t s = (hipStream_t)stream;
     float *sa = nullptr, *sb = nullptr;
     if (plane != 1) {
-        hipError_t e = hipMalloc((void **)&sa, sizeof(float) * n);
-        if (e == hipSuccess) e = hipMalloc((void **)&sb, sizeof(float) * n);
-        if (e != hipSuccess) {
-            if (sa) (void)hipFree(sa);
-            return hip_fail(e, "msf_denoise25 workspace");
+        // the network keeps two sequence volumes; a larger volume replaces them
+        if (n > C->seq_cap) {
+            if (C->seq) {
+                CHK(hipStreamSynchronize(s));
+                (void)hipFree(C->seq);
+            }
+            C->seq = nullptr;
+            C->seq_cap = 0;
+            CHK(cnn_alloc(&C->seq, (size_t)(2 * n)));
+            C->seq_cap = n;
         }
+        sa = C->seq;
+        sb = C->seq + n;
     }
-    hipError_t e = denoise25_internal(C, w, n_frames, nz, ny, nx, plane, out, sa, sb, s);
-    if (e == hipSuccess && plane != 1) e = hipStreamSynchronize(s);
-    if (sa) (void)hipFree(sa);
-    if (sb) (void)hipFree(sb);
-    if (e != hipSuccess) return hip_fail(e, "msf_denoise25");
+    CHK(denoise25_internal(C, w, n_frames, nz, ny, nx, plane, out, sa, sb, s));
     return MSF_OK;
 }
 
