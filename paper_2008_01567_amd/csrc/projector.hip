@@ -59,6 +59,16 @@ __device__ __forceinline__ double row_f64(__amdgpu_buffer_rsrc_t r, int idx)
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
 }
+// element idx + 1: the constant goes into the instruction's offset field,
+// which the range check includes (reads past the row still give 0)
+__device__ __forceinline__ float row_f32_next(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4 + 4, 0, 0));
+}
+__device__ __forceinline__ double row_f64_next(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8 + 8, 0, 0));
+}
 
 // Parameter of the crossing with plane k of an axis: s = k * inv + c0, with
 // inv = 1/e (direction component) and c0 = (-half - f) * inv.  Every kernel
@@ -723,9 +733,9 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         ima[k] = row_f64(irow, iva[k]);
-        imb[k] = row_f64(irow, iva[k] + 1);
+        imb[k] = row_f64_next(irow, iva[k]);
         sva[k] = row_f32(srow, iva[k]);
-        svb[k] = row_f32(srow, iva[k] + 1);
+        svb[k] = row_f32_next(srow, iva[k]);
     }
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
