@@ -38,10 +38,10 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "d01157aa19d1d5e6b9036e375c6d923f2a659347ca4dbf82f52f38387312543b",
+    "source_sha256": "68deed2929eee5de7869def05bec594b0debebd727c1054e4e80bd4cacc17b01",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
-    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.1e6,
-    "read_bytes": 987.2e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.933,
+    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.0e6,
+    "read_bytes": 987.1e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.933,
     "profile": "profiles/gather_update_c2_128x16_counters.md",
 }
 
