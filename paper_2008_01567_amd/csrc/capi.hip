@@ -72,6 +72,16 @@ void row_range(msf_plan &P)
     const double vmax = std::max(std::fabs((P.iv_lo - 0.5 * (P.nv - 1)) * P.dv + P.offv),
                                  std::fabs((P.iv_hi - 0.5 * (P.nv - 1)) * P.dv + P.offv));
     P.steep = vmax / P.rsd * std::sqrt(2.0) >= 0.999;
+    // Detector rows whose ray meets one voxel (height 1) inside one xy piece:
+    // the ray's detector height per unit z is k = l_xy / d (d = xy distance from
+    // the source >= src_iso - r_max), so over the voxel and the piece (at most
+    // sqrt(2) long) zp spans at most k_max + (nz / 2) |k_b - k_a| with k_max =
+    // lmax / dmin and |k_b - k_a| <= lmax sqrt(2) / dmin^2.  Below two rows
+    // (with the gather's 2e-3 widening) every voxel meets at most two
+    // consecutive rows per piece, the two candidates the gather always reads.
+    const double dmin = P.rs - rmax;
+    const double span = (lmax / dmin + 0.5 * P.nz * lmax * std::sqrt(2.0) / (dmin * dmin)) / P.dv + 2e-3;
+    P.multi_row = span >= 1.9;
 }
 
 // Rays per lane: one wave covers all rows of a detector column that can meet

@@ -59,6 +59,7 @@ struct ProjParams {
     int n_vc;                    // row chunks per column
     int rows_per_chunk;          // 64 * rays_per_lane
     int iv_lo, iv_hi;            // detector rows that can meet the volume
+    int multi_row;               // a ray may meet one voxel within one xy piece in three or more rows
     int xcd_remap;
     int64_t nvox;                // voxels per frame
     int64_t total_tiles;
@@ -116,6 +117,7 @@ struct msf_plan {
     int64_t n_views = 0, nvox = 0, nvox_total = 0, nmeas_total = 0;
     int iv_lo = 0, iv_hi = -1;
     bool steep = false;                   // some ray may cross two z planes inside one xy cell
+    bool multi_row = true;                // some ray may meet one voxel within one xy piece in 3+ rows
     msf_tiles tiles{};
     std::vector<int64_t> tile_offset;     // host copy of the projector tile prefix
     int64_t vol_blocks_per_frame = 0;     // blocks of the volume kernels per frame

@@ -714,15 +714,13 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
     const float c_lo = c0 - 1e-3f, c_hi = c0 + 1e-3f;
     const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino + (v * P.nu + iu) * (int64_t)P.nv, P.nv * 4);
     const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + (int64_t)iu * P.nv, P.nv * 8);
-    int iva[ZPL], ivb[ZPL];
+    int iva[ZPL];
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         // rows through [zlo, zhi] within [fa, fb]: zp between z * ka and z * kb
         const float zlo = iz[k] - hzf;
-        const float a0 = zlo * ka, b0 = zlo * kb;
-        const float zp_lo = fminf(a0, b0), zp_hi = fmaxf(a0 + ka, b0 + kb);
+        const float zp_lo = fminf(zlo * ka, zlo * kb);
         iva[k] = max((int)ceilf(fmaf(zp_lo, inv_dv, c_lo)), P.iv_lo);
-        ivb[k] = min((int)floorf(fmaf(zp_hi, inv_dv, c_hi)), P.iv_hi);
     }
     // the first two candidate rows of every voxel without a branch.  Reads past a
     // row give 0, and a row outside [iva, ivb] misses the voxel inside the piece, so
@@ -742,10 +740,15 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
         const float la = fmaxf(slab_piece(ima[k], sf, klo[k], fa, fb), 0.0f);
         const float lb = fmaxf(slab_piece(imb[k], sf, klo[k], fa, fb), 0.0f);
         float acc_k = fmaf(lb, svb[k], fmaf(la, sva[k], vacc[k]));
-        // the rare further candidates
-        for (int ivr = iva[k] + 2; ivr <= ivb[k]; ++ivr) {
-            const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
-            if (l > 0.0f) acc_k = fmaf(l, row_f32(srow, ivr), acc_k);
+        if (P.multi_row) {
+            // geometries where a ray can meet a voxel in three or more rows: the further candidates
+            const float zlo = iz[k] - hzf;
+            const float zp_hi = fmaxf(fmaf(zlo, ka, ka), fmaf(zlo, kb, kb));
+            const int ivb = min((int)floorf(fmaf(zp_hi, inv_dv, c_hi)), P.iv_hi);
+            for (int ivr = iva[k] + 2; ivr <= ivb; ++ivr) {
+                const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
+                if (l > 0.0f) acc_k = fmaf(l, row_f32(srow, ivr), acc_k);
+            }
         }
         vacc[k] = acc_k;
     }
@@ -914,6 +917,7 @@ ProjParams msf_plan::proj_params(bool with_active) const
     pp.rows_per_chunk = WAVE * tiles.rays_per_lane;
     pp.iv_lo = iv_lo;
     pp.iv_hi = iv_hi;
+    pp.multi_row = multi_row ? 1 : 0;
     pp.n_vc = iv_hi >= iv_lo ? (iv_hi - iv_lo + pp.rows_per_chunk) / pp.rows_per_chunk : 0;
     pp.xcd_remap = tiles.xcd_remap;
     pp.nvox = nvox;

@@ -131,3 +131,28 @@ def test_truncated_detector(msf, back):
     got_b = plan.backproject(_dev(yy)).cpu().numpy()
     for f in range(g.n_frames):
         assert rel_l2(got_b[f], want_b[f]) <= 2e-6
+
+
+@pytest.mark.parametrize("pitch,det,back", [(0.6, 64, 2), (0.6, 64, 1), (0.4, 96, 1)])
+def test_fine_detector_rows(msf, pitch, det, back):
+    """Detector pitch 0.6 and 0.4 voxel at the isocentre: a ray can meet one voxel
+    in three or four detector rows inside one xy piece, so the gathers take their
+    path for rows beyond the two candidates they always read (at pitch 0.4 more
+    than three columns meet a cell, so only the on-the-fly gather applies); A and
+    A^T against the oracle."""
+    import dataclasses
+    print("pitch", pitch, "back", back, flush=True)
+    cfg = dataclasses.replace(synth.config("c1"), det=(det, det), pitch_at_iso=pitch, cid=63)
+    g = synth.make_geometry(cfg)
+    x0 = synth.make_phantom(cfg).astype(np.float32).astype(np.float64)
+    plan = msf.Plan(g)
+    plan.set_tiles(back_mode=back)
+    want = oracle.project(g, x0)
+    got = plan.project(_dev(x0)).cpu().numpy()
+    assert _frame_rel(g, got, want) <= 2e-6
+    rng = np.random.default_rng(64)
+    yy = rng.uniform(0.5, 1.5, size=plan.n_meas).astype(np.float32).astype(np.float64)
+    want_b = oracle.backproject(g, yy)
+    got_b = plan.backproject(_dev(yy)).cpu().numpy()
+    for f in range(g.n_frames):
+        assert rel_l2(got_b[f], want_b[f]) <= 2e-6
