@@ -703,7 +703,7 @@ __global__ void k_cell_table(const ProjParams P, int64_t n_views, int32_t *__res
 // passes through the voxel inside the piece.  All row indices first, then all
 // loads, then the arithmetic: one wait for the whole column.
 template <int ZPL>
-__device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino, int64_t v, int iu, double sf,
+__device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino_v, int iu, double sf,
                                               float fa, float fb, float ka, float kb, const int (&iz)[ZPL],
                                               const double (&klo)[ZPL], float (&vacc)[ZPL])
 {
@@ -712,8 +712,10 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
     const float inv_dv = (float)(1.0 / P.dv);
     const float c0 = (float)(0.5 * (P.nv - 1) - P.offv / P.dv);
     const float c_lo = c0 - 1e-3f, c_hi = c0 + 1e-3f;
-    const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino + (v * P.nu + iu) * (int64_t)P.nv, P.nv * 4);
-    const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + (int64_t)iu * P.nv, P.nv * 8);
+    // sino_v: the view's sinogram; nu * nv < 2^31, so the column offset is 32-bit
+    const int coff = iu * P.nv;
+    const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino_v + coff, P.nv * 4);
+    const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + coff, P.nv * 8);
     int iva[ZPL];
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
@@ -785,27 +787,32 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
         acc[k] = 0.0;
     }
     const int64_t v0 = col_ok ? P.view_offset[f] : 0, v1 = col_ok ? P.view_offset[f + 1] : 0;
+    const int64_t view_len = (int64_t)P.nu * P.nv;
     if constexpr (KT > 0) {
         const int64_t ncell = (int64_t)P.nx * P.ny;
         const int64_t cell = (int64_t)iy * P.nx + ix;
+        // the (view, cell) slots of consecutive views are ncell apart
+        const int32_t *hdr = P.cell_hdr + v0 * ncell + cell;
+        const CellEntry *ent = P.cell_ent + (v0 * ncell + cell) * KT;
+        const float *sino_v = sino + v0 * view_len;
         int n_next = 0;
         CellEntry e_next[KT];
         if (v0 < v1) {
-            const int64_t slot = v0 * ncell + cell;
-            n_next = P.cell_hdr[slot];
+            n_next = *hdr;
 #pragma unroll
-            for (int j = 0; j < KT; ++j) e_next[j] = P.cell_ent[slot * KT + j];
+            for (int j = 0; j < KT; ++j) e_next[j] = ent[j];
         }
-        for (int64_t v = v0; v < v1; ++v) {
+        for (int64_t v = v0; v < v1; ++v, sino_v += view_len) {
             const int n = n_next;
             CellEntry ec[KT];
 #pragma unroll
             for (int j = 0; j < KT; ++j) ec[j] = e_next[j];
             if (v + 1 < v1) {
-                const int64_t slot = (v + 1) * ncell + cell;
-                n_next = P.cell_hdr[slot];
+                hdr += ncell;
+                ent += ncell * KT;
+                n_next = *hdr;
 #pragma unroll
-                for (int j = 0; j < KT; ++j) e_next[j] = P.cell_ent[slot * KT + j];
+                for (int j = 0; j < KT; ++j) e_next[j] = ent[j];
             }
             float vacc[ZPL];
 #pragma unroll
@@ -814,7 +821,7 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
             for (int j = 0; j < KT; ++j) {
                 if (j >= n) break;
                 // canonical once here, so the per-voxel min / max need no canonicalisation
-                gather_column<ZPL>(P, sino, v, ec[j].iu, ec[j].sf, __builtin_canonicalizef(ec[j].fa),
+                gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, __builtin_canonicalizef(ec[j].fa),
                                    __builtin_canonicalizef(ec[j].fb), ec[j].ka, ec[j].kb, iz, klo, vacc);
             }
 #pragma unroll
@@ -833,7 +840,7 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 const ColEntry &E = P.cols[v * P.nu + iu];
                 float fa, fb, ka, kb;
                 if (!cell_piece(E, ix, iy, fa, fb, ka, kb)) continue;
-                gather_column<ZPL>(P, sino, v, iu, E.sf, __builtin_canonicalizef(fa), __builtin_canonicalizef(fb),
+                gather_column<ZPL>(P, sino + v * view_len, iu, E.sf, __builtin_canonicalizef(fa), __builtin_canonicalizef(fb),
                                    ka, kb, iz, klo, vacc);
             }
 #pragma unroll
