@@ -38,10 +38,10 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "68deed2929eee5de7869def05bec594b0debebd727c1054e4e80bd4cacc17b01",
+    "source_sha256": "168b2c42d36b28e4239ba95a111d40deb0e8708c8238f10d1027aae6b0a96c3a",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
-    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.0e6,
-    "read_bytes": 987.1e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.933,
+    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.5e6,
+    "read_bytes": 987.6e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.932,
     "profile": "profiles/gather_update_c2_128x16_counters.md",
 }
 
