@@ -142,8 +142,10 @@ msf_status msf_plan_set_tiles(msf_plan *plan, const msf_tiles *tiles);
 msf_status msf_plan_get_tiles(const msf_plan *plan, msf_tiles *tiles);
 
 /* Autotuner: times the forward projector with the voxel-driven adjoint (HIP
- * events on the given stream, plan-owned buffers) for every supported launch
- * shape on this plan's geometry, then the ray-driven adjoint at the best
+ * events on the given stream, plan-owned buffers; the better of two runs
+ * after a warm-up run) for every supported launch shape on this plan's
+ * geometry, with the on-the-fly and the table-driven adjoint (the latter
+ * with the forward's walk table), then the ray-driven adjoint at the best
  * shape, and applies the fastest (forward + adjoint) pair.
  * cache_path (may be NULL): text file of "key tiles" lines, key = GPU arch +
  * geometry sizes + a hash of the angle list; a hit is applied without timing,

@@ -245,7 +245,8 @@ __device__ __forceinline__ Pieces ray_pieces_open(const RayZ &z, float scur, flo
 {
     Pieces q;
     q.cross = z.szn < snext;
-    const float mid = q.cross ? fmaxf(z.szn, scur) : snext;
+    // cross ? max(szn, scur) : snext, as one median (scur <= snext along the walk)
+    const float mid = __builtin_amdgcn_fmed3f(z.szn, scur, snext);
     q.l1 = mid - scur;
     q.l2 = q.cross ? snext - mid : 0.0f;
     q.iz = z.iz;
@@ -827,9 +828,8 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
 #pragma unroll
             for (int j = 0; j < KT; ++j) {
                 if (j >= n) break;
-                // canonical once here, so the per-voxel min / max need no canonicalisation
-                gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, __builtin_canonicalizef(ec[j].fa),
-                                   __builtin_canonicalizef(ec[j].fb), ec[j].ka, ec[j].kb, iz, klo, vacc);
+                gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, ec[j].fa, ec[j].fb, ec[j].ka, ec[j].kb, iz, klo,
+                                   vacc);
             }
 #pragma unroll
             for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
@@ -847,7 +847,7 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 const ColEntry &E = P.cols[v * P.nu + iu];
                 float fa, fb, ka, kb;
                 if (!cell_piece(E, ix, iy, fa, fb, ka, kb)) continue;
-                gather_column<ZPL>(P, sino + v * view_len, iu, E.sf, __builtin_canonicalizef(fa), __builtin_canonicalizef(fb),
+                gather_column<ZPL>(P, sino + v * view_len, iu, E.sf, fa, fb,
                                    ka, kb, iz, klo, vacc);
             }
 #pragma unroll
