@@ -17,9 +17,10 @@
 // Every layer is an implicit GEMM on the matrix cores: channels-last BF16
 // activations [N][Z][Y][X][16] (the 2- or 5-channel input and the 1-channel
 // output are zero-padded to 16), and for each tap one
-// v_mfma_f32_16x16x16_bf16 multiplies 16 output voxels x 16 input channels by
-// the tap's 16 x 16 weight block, accumulating in FP32; taps that fall outside
-// the volume in y or z are skipped for the whole wave.  The input gradient is
+// v_mfma_f32_16x16x16_bf16 multiplies the tap's 16 x 16 weight block by 16
+// voxels x 16 input channels, accumulating in FP32.  Input rows are staged in
+// LDS by workgroup tiles (2D images: row tiles; 3D volumes: row tiles sliding
+// along z with a three-slice ring), zero outside the volume.  The input gradient is
 // the same kernel run with the spatially flipped, channel-transposed weights;
 // the weight gradient is a split-K MFMA GEMM over voxels with a fixed-order
 // reduction of the per-wave partial sums.  Master weights and Adam moments are
@@ -154,88 +155,6 @@ __device__ __forceinline__ void conv_store(const ConvArgs &A, const v4f &acc, co
 __device__ __forceinline__ float4 conv_bias(const ConvArgs &A, int g)
 {
     return A.bias ? *reinterpret_cast<const float4 *>(A.bias + 4 * g) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-}
-
-// one wave: 16 consecutive x voxels of one (n, z, y) row, all 16 output
-// channels, one MFMA per tap
-struct SegPos {
-    int n, z, y, x0;
-};
-
-__device__ __forceinline__ SegPos seg_pos(int64_t seg, int nsx, int Y, int Z)
-{
-    SegPos p;
-    int64_t t = seg;
-    p.x0 = (int)(t % nsx) * 16; t /= nsx;
-    p.y = (int)(t % Y); t /= Y;
-    p.z = (int)(t % Z);
-    p.n = (int)(t / Z);
-    return p;
-}
-
-// The NT = 9 NDZ tap inputs of a segment: lane (r, g) holds voxel x0 + r + dx
-// - 1, input channels 4g .. 4g + 3 (zero outside the volume).  NDZ = 1 reads
-// the depth-centre taps only (exact for depth-1 images).
-template <int NDZ>
-__device__ __forceinline__ void load_taps(const ConvArgs &A, const SegPos &p, int r, int g, v4s *a)
-{
-#pragma unroll
-    for (int t = 0; t < NDZ * 9; ++t) {
-        const int dz = NDZ == 1 ? 1 : t / 9, dy = (t / 3) % 3, dx = t % 3;
-        const int zz = p.z + dz - 1, yy = p.y + dy - 1, xx = p.x0 + r + dx - 1;
-        const bool ok = zz >= 0 && zz < A.Z && yy >= 0 && yy < A.Y && xx >= 0 && xx < A.X;
-        const int64_t vox = (((int64_t)p.n * A.Z + zz) * A.Y + yy) * A.X + xx;
-        a[t] = ok ? *reinterpret_cast<const v4s *>(A.in + vox * CH + 4 * g) : v4s{0, 0, 0, 0};
-    }
-}
-
-// All tap inputs of a segment are loaded before its MFMAs, and the next
-// segment's while the current one is multiplied (latency of the gathers
-// hidden behind a whole segment of work).
-template <int EPI, int NDZ>
-__global__ __launch_bounds__(256) void k_conv(const ConvArgs A)
-{
-    constexpr int NT = NDZ * 9;
-    constexpr int T0 = NDZ == 1 ? 9 : 0;                // first kernel tap used
-    __shared__ v4s wl[NT * CH * 4];   // [tap][out][k-group]: 4 input channels each
-    const v4s *wsrc = reinterpret_cast<const v4s *>(A.w) + T0 * CH * 4;
-    for (int i = threadIdx.x; i < NT * CH * 4; i += blockDim.x) wl[i] = wsrc[i];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = lane & 15, g = lane >> 4;
-    const int nsx = (A.X + 15) / 16;
-    const int64_t nseg = (int64_t)A.N * A.Z * A.Y * nsx;
-    const int64_t stride = (int64_t)gridDim.x * 4;
-    int64_t seg = (int64_t)blockIdx.x * 4 + wave;
-    if (seg >= nseg) return;
-    const float4 bias = conv_bias(A, g);
-    SegPos p = seg_pos(seg, nsx, A.Y, A.Z);
-    v4s cur[NT];
-    load_taps<NDZ>(A, p, r, g, cur);
-    for (; seg < nseg; seg += stride) {
-        const int64_t sn = seg + stride;
-        SegPos pn = p;
-        v4s nxt[NT];
-        if (sn < nseg) {
-            pn = seg_pos(sn, nsx, A.Y, A.Z);
-            load_taps<NDZ>(A, pn, r, g, nxt);
-        }
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[t * (CH * 4) + r * 4 + g], cur[t], acc, 0, 0, 0);
-        const int xv = p.x0 + r;
-        if (xv < A.X) {
-            const int64_t vox = (((int64_t)p.n * A.Z + p.z) * A.Y + p.y) * A.X + xv;
-            const int64_t vres = (int64_t)p.n * A.v_stride + A.v_off + ((int64_t)p.z * A.Y + p.y) * A.X + xv;
-            conv_store<EPI>(A, acc, bias, vox, vres, g);
-        }
-        if (sn < nseg) {
-            p = pn;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
-        }
-    }
 }
 
 // Depth-1 images (the 2.5D denoiser): a workgroup owns a tile of TY rows x
@@ -385,6 +304,101 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
             if (xv < A.X)
                 conv_store<EPI>(A, acc, bias, ((int64_t)pc.n * A.Y + y) * A.X + xv,
                                 (int64_t)pc.n * A.v_stride + A.v_off + (int64_t)y * A.X + xv, g);
+        }
+    }
+}
+
+// 3D volumes: a workgroup owns TY3 rows x 64 voxels of ZC3 consecutive z
+// slices of one volume and slides along z, keeping the three input slices
+// z - 1, z, z + 1 (each with a one-voxel halo in y and x) in an LDS ring; one
+// new slice is staged per output slice (16-byte loads, the slice after it
+// prefetched into registers), so each input voxel is read about
+// (TY3 + 2) / TY3 times instead of 27.
+constexpr int TY3 = 4, ZC3 = 16;
+constexpr int SL_VOX = (TY3 + 2) * TROW;         // staged voxels per slice
+constexpr int SL_U4 = 2 * SL_VOX;                 // 16-byte chunks per slice
+constexpr int SL_LD = (SL_U4 + 255) / 256;        // per thread
+
+__device__ __forceinline__ void slice_fetch(const ConvArgs &A, int n, int z, int y0, int x0, uint4 (&reg)[SL_LD])
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(A.in);
+#pragma unroll
+    for (int k = 0; k < SL_LD; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        const int row = idx / (2 * TROW), rem = idx - row * (2 * TROW);
+        const int gy = y0 - 1 + row, gx = x0 - 1 + (rem >> 1);
+        const bool ok = idx < SL_U4 && z >= 0 && z < A.Z && gy >= 0 && gy < A.Y && gx >= 0 && gx < A.X;
+        reg[k] = ok ? src[((((int64_t)n * A.Z + z) * A.Y + gy) * A.X + gx) * 2 + (rem & 1)] : make_uint4(0, 0, 0, 0);
+    }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv3d(const ConvArgs A)
+{
+    __shared__ v4s wl[TAPS * CH * 4];
+    __shared__ uint4 ring[3 * SL_U4];
+    const v4s *wsrc = reinterpret_cast<const v4s *>(A.w);
+    for (int i = threadIdx.x; i < TAPS * CH * 4; i += blockDim.x) wl[i] = wsrc[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int ntx = (A.X + TXW - 1) / TXW, nty = (A.Y + TY3 - 1) / TY3, nzc = (A.Z + ZC3 - 1) / ZC3;
+    int64_t t = blockIdx.x;
+    const int x0 = (int)(t % ntx) * TXW;
+    t /= ntx;
+    const int y0 = (int)(t % nty) * TY3;
+    t /= nty;
+    const int zbeg = (int)(t % nzc) * ZC3;
+    const int n = (int)(t / nzc);
+    const int zend = min(zbeg + ZC3, A.Z);
+    const float4 bias = conv_bias(A, g);
+    const int xs = x0 + 16 * wave;           // this wave's segment
+    // ring slot of slice z (z >= zbeg - 1)
+    auto slot = [&](int z) { return (z - zbeg + 1) % 3; };
+    uint4 reg[SL_LD];
+    slice_fetch(A, n, zbeg - 1, y0, x0, reg);
+#pragma unroll
+    for (int k = 0; k < SL_LD; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        if (idx < SL_U4) ring[slot(zbeg - 1) * SL_U4 + idx] = reg[k];
+    }
+    slice_fetch(A, n, zbeg, y0, x0, reg);
+#pragma unroll
+    for (int k = 0; k < SL_LD; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        if (idx < SL_U4) ring[slot(zbeg) * SL_U4 + idx] = reg[k];
+    }
+    slice_fetch(A, n, zbeg + 1, y0, x0, reg);
+    const v4s *tl = reinterpret_cast<const v4s *>(ring);
+    for (int z = zbeg; z < zend; ++z) {
+        __syncthreads();                     // slice z - 2 (the slot of z + 1) is no longer read
+#pragma unroll
+        for (int k = 0; k < SL_LD; ++k) {
+            const int idx = threadIdx.x + 256 * k;
+            if (idx < SL_U4) ring[slot(z + 1) * SL_U4 + idx] = reg[k];
+        }
+        __syncthreads();
+        if (z + 2 <= zend) slice_fetch(A, n, z + 2, y0, x0, reg);
+        if (xs >= A.X) continue;             // wave-uniform; barriers only at the top of the loop
+        for (int ry = 0; ry < TY3 && y0 + ry < A.Y; ++ry) {
+            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) {
+                const int sb = slot(z - 1 + dz) * SL_VOX;
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const v4s a = tl[(sb + (ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                            wl[((dz * 3 + dy) * 3 + dx) * (CH * 4) + r * 4 + g], a, acc, 0, 0, 0);
+                    }
+            }
+            const int y = y0 + ry, xv = xs + r;
+            if (xv < A.X) {
+                const int64_t row = ((int64_t)n * A.Z + z) * A.Y + y;
+                conv_store<EPI>(A, acc, bias, row * A.X + xv,
+                                (int64_t)n * A.v_stride + A.v_off + ((int64_t)z * A.Y + y) * A.X + xv, g);
+            }
         }
     }
 }
@@ -632,9 +646,7 @@ hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const flo
                        int64_t v_off, float scale, hipStream_t s)
 {
     ConvArgs A{in, w, bias, N, Z, Y, X, out_bf, mask, out_f, v, v_stride, v_off, scale};
-    const int64_t nseg = (int64_t)N * Z * Y * ((X + 15) / 16);
-    // about 8 segments per wave when there is enough work, at most 32 blocks per CU
-    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((nseg + 31) / 32, 8192))), block(256);
+    const dim3 block(256);
     if (Z == 1) {
         // depth-1 images: only the depth-centre taps can be non-zero; row tiles staged in LDS
         const int64_t ntile = (int64_t)N * ((Y + TY - 1) / TY) * ((X + TXW - 1) / TXW);
@@ -646,10 +658,14 @@ hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const flo
         }
         return hipGetLastError();
     }
+    // 3D volumes: z-sliding row tiles
+    const int64_t ntile3 = (int64_t)N * ((Z + ZC3 - 1) / ZC3) * ((Y + TY3 - 1) / TY3) * ((X + TXW - 1) / TXW);
+    if (ntile3 > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 g3((unsigned)ntile3);
     switch (epi) {
-    case EPI_RELU: hipLaunchKernelGGL((k_conv<EPI_RELU, 3>), grid, block, 0, s, A); break;
-    case EPI_MASK: hipLaunchKernelGGL((k_conv<EPI_MASK, 3>), grid, block, 0, s, A); break;
-    default: hipLaunchKernelGGL((k_conv<EPI_RESID, 3>), grid, block, 0, s, A); break;
+    case EPI_RELU: hipLaunchKernelGGL((k_conv3d<EPI_RELU>), g3, block, 0, s, A); break;
+    case EPI_MASK: hipLaunchKernelGGL((k_conv3d<EPI_MASK>), g3, block, 0, s, A); break;
+    default: hipLaunchKernelGGL((k_conv3d<EPI_RESID>), g3, block, 0, s, A); break;
     }
     return hipGetLastError();
 }
