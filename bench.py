@@ -246,7 +246,10 @@ def main():
                              "non-packed FP32 FMA rate 256 CU x 64 lanes x 2 x 2.4 GHz; traffic = HBM bytes per "
                              "launch from rocprofv3 FETCH_SIZE+WRITE_SIZE scaled by a copy kernel (null when the "
                              "kernel or launch shape differs from the profiled one)",
-                     "hbm_gbs_of_traffic": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9},
+                     "hbm_gbs_of_traffic": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9,
+                     "hbm_frac_of_traffic": None if traffic is None else
+                     traffic / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "l2_hit_rate": None if traffic is None else MEASURED_TRAFFIC["l2_hit_rate"]},
     }
     if not args.no_agents:
         result["denoiser_agents"] = time_agents(msf, torch, out, dev)
