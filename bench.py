@@ -42,6 +42,8 @@ MEASURED_TRAFFIC = {
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
     "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.5e6,
     "read_bytes": 987.6e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.932,
+    # SQ_INSTS_VALU x 64 / nnz(A) of the same runs: VALU lane-instructions per intersection
+    "valu_lane_instr_per_intersection": 31.6,
     "profile": "profiles/gather_update_c2_128x16_counters.md",
 }
 
@@ -238,6 +240,8 @@ def main():
             "start_rel_residual": float(np.mean(st["start_rel_residual"]))},
         "speedup_learned_vs_plain": None if net is None else dt_plain / dt,
         "kernels_ms": {"forward": fwd_ms, "back": back_ms, "timed_launches": tm["forward_launches"]},
+        "projector_voxel_views_per_s": {"forward": voxel_views / (fwd_ms * 1e-3),
+                                        "back": voxel_views / (back_ms * 1e-3)},
         "nnz_A": nnz_total,
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
@@ -249,7 +253,12 @@ def main():
                      "hbm_gbs_of_traffic": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9,
                      "hbm_frac_of_traffic": None if traffic is None else
                      traffic / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                     "l2_hit_rate": None if traffic is None else MEASURED_TRAFFIC["l2_hit_rate"]},
+                     "l2_hit_rate": None if traffic is None else MEASURED_TRAFFIC["l2_hit_rate"],
+                     # the kernel against its instruction-issue bound: the VALU lane-instructions it
+                     # executes per intersection (counters) at 39.3 T lane-instructions/s, over its time
+                     "issue_bound_frac": None if traffic is None else
+                     nnz_total * MEASURED_TRAFFIC["valu_lane_instr_per_intersection"] / (PEAK_ALU_TFLOPS * 0.5e12)
+                     / (dom_ms * 1e-3)},
     }
     if not args.no_agents:
         result["denoiser_agents"] = time_agents(msf, torch, out, dev)
