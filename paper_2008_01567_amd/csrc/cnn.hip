@@ -308,6 +308,95 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
     }
 }
 
+// First layer of the 2.5D denoiser on a plane sequence [T][S][H][W] (IN_SEQ):
+// a workgroup owns one (slice s, 8-row, 64-voxel) tile and walks along the
+// time points [t0, t1) of the chunk, keeping the tile of frames t - 2 .. t + 2
+// (one BF16 channel each, scaled as the input pack does) in a five-slot LDS
+// ring: each frame is staged once per tile instead of five times.  Frame
+// t + 3 is loaded into registers while time point t is multiplied.
+constexpr int RING_VOX = (TY + 2) * TROW;
+constexpr int RING_LD = (RING_VOX + 255) / 256;
+
+__device__ __forceinline__ void frame_fetch(const ConvArgs &A, int f, int s, int y0, int x0, float (&reg)[RING_LD])
+{
+    const PackIn &P = A.pin;
+    const int64_t per = (int64_t)A.Y * A.X;
+    const float *src = P.a + ((int64_t)f * P.S + s) * per;
+#pragma unroll
+    for (int k = 0; k < RING_LD; ++k) {
+        const int vi = threadIdx.x + 256 * k;
+        const int row = vi / TROW, col = vi - row * TROW;
+        const int gy = y0 - 1 + row, gx = x0 - 1 + col;
+        const bool ok = vi < RING_VOX && f >= 0 && f < P.T && gy >= 0 && gy < A.Y && gx >= 0 && gx < A.X;
+        reg[k] = ok ? src[(int64_t)gy * A.X + gx] * P.inv0 : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int t0, int t1)
+{
+    __shared__ v4s wl[9 * CH * 4];
+    __shared__ uint16_t ring[5 * RING_VOX];
+    const v4s *wsrc = reinterpret_cast<const v4s *>(A.w) + 9 * CH * 4;     // the depth-centre taps
+    for (int i = threadIdx.x; i < 9 * CH * 4; i += blockDim.x) wl[i] = wsrc[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int T = A.pin.T, S = A.pin.S;
+    const int ntx = (A.X + TXW - 1) / TXW, nty = (A.Y + TY - 1) / TY;
+    int64_t b = blockIdx.x;
+    const int x0 = (int)(b % ntx) * TXW;
+    b /= ntx;
+    const int y0 = (int)(b % nty) * TY;
+    const int si = (int)(b / nty);
+    const float4 bias = conv_bias(A, g);
+    const int xs = x0 + 16 * wave;
+    float reg[RING_LD];
+    auto stage = [&](int f) {
+#pragma unroll
+        for (int k = 0; k < RING_LD; ++k) {
+            const int vi = threadIdx.x + 256 * k;
+            if (vi < RING_VOX) ring[(f % 5) * RING_VOX + vi] = f2bf(reg[k]);
+        }
+    };
+    // frames max(t0 - 2, 0) .. t0 + 2 (those that exist)
+    for (int f = max(t0 - 2, 0); f <= min(t0 + 2, T - 1); ++f) {
+        frame_fetch(A, f, si, y0, x0, reg);
+        stage(f);
+    }
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();                     // frame t + 2 staged; frame t - 3's slot no longer read
+        const int fn = t + 3;
+        if (fn < T) frame_fetch(A, fn, si, y0, x0, reg);
+        if (xs < A.X) {
+            // channel c of this lane (c = 4g + j < 5) reads frame clamp(t + c - 2)
+            int sb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * g + j;
+                sb[j] = c < 5 ? (min(max(t + c - 2, 0), T - 1) % 5) * RING_VOX : -1;
+            }
+            const int64_t n = (int64_t)t * S + si - (int64_t)A.pin.n0;     // image within the chunk
+            for (int ry = 0; ry < TY && y0 + ry < A.Y; ++ry) {
+                v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const int o = (ry + dy) * TROW + 16 * wave + r + dx;
+                        v4s a;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) a[j] = sb[j] >= 0 ? (short)ring[sb[j] + o] : (short)0;
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[(dy * 3 + dx) * (CH * 4) + r * 4 + g], a,
+                                                                        acc, 0, 0, 0);
+                    }
+                const int y = y0 + ry, xv = xs + r;
+                if (xv < A.X) conv_store<EPI_RELU>(A, acc, bias, (n * A.Y + y) * A.X + xv, 0, g);
+            }
+        }
+        __syncthreads();                     // every read of frame t - 2 (the slot of t + 3) is done
+        if (fn < T) stage(fn);
+    }
+}
+
 // 3D volumes: a workgroup owns TY3 rows x 64 voxels of ZC3 consecutive z
 // slices of one volume and slides along z, keeping the three input slices
 // z - 1, z, z + 1 (each with a one-voxel halo in y and x) in an LDS ring; one
@@ -681,9 +770,17 @@ hipError_t cnn_forward(msf_cnn *C, const PackIn &in, int N, int Z, int Y, int X,
     if (Z == 1 && !keep_input) {
         // depth-1 inference: the first layer stages its input from the FP32 sources
         ConvArgs A{nullptr, C->wf, C->bias, N, Z, Y, X, C->h[1], nullptr, nullptr, nullptr, 0, 0, 0.0f, in};
-        const int64_t ntile = (int64_t)N * ((Y + TY - 1) / TY) * ((X + TXW - 1) / TXW);
-        const dim3 g2((unsigned)std::max<int64_t>(1, std::min<int64_t>(ntile, 4096)));
-        hipLaunchKernelGGL((k_conv2d<EPI_RELU, true>), g2, dim3(256), 0, s, A);
+        const int64_t tiles_per_image = (int64_t)((Y + TY - 1) / TY) * ((X + TXW - 1) / TXW);
+        if (in.mode == IN_SEQ && in.n0 % in.S == 0 && N % in.S == 0 && (int64_t)in.S * tiles_per_image <= 0x7fffffff) {
+            // whole time points: walk along t with the five-frame ring
+            const int t0 = (int)(in.n0 / in.S), t1 = t0 + N / in.S;
+            hipLaunchKernelGGL(k_conv2d_first_seq, dim3((unsigned)(in.S * tiles_per_image)), dim3(256), 0, s, A, t0,
+                               t1);
+        } else {
+            const int64_t ntile = (int64_t)N * tiles_per_image;
+            const dim3 g2((unsigned)std::max<int64_t>(1, std::min<int64_t>(ntile, 4096)));
+            hipLaunchKernelGGL((k_conv2d<EPI_RELU, true>), g2, dim3(256), 0, s, A);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         l0 = 1;
     } else {
@@ -807,8 +904,10 @@ hipError_t denoise_sequence(msf_cnn *C, const float *seq, int T, int S, int H, i
 {
     const int64_t per = (int64_t)H * W;
     const int64_t N = (int64_t)T * S;
-    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)1 << 26) / per));
-    hipError_t e = cnn_reserve(C, (int64_t)chunk * per);
+    // chunks of whole time points when S images fit (the first layer then walks along t)
+    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)1 << 26) / per));
+    if (chunk >= S) chunk -= chunk % S;
+    hipError_t e = cnn_reserve(C, chunk * per);
     if (e != hipSuccess) return e;
     PackIn P{};
     P.mode = IN_SEQ;
@@ -817,7 +916,7 @@ hipError_t denoise_sequence(msf_cnn *C, const float *seq, int T, int S, int H, i
     P.S = S;
     P.inv0 = 1.0f / C->cv;
     for (int64_t f0 = 0; f0 < N; f0 += chunk) {
-        const int nf = (int)std::min<int64_t>(chunk, N - f0);
+        const int nf = (int)std::min<int64_t>(chunk, N - f0);     // a multiple of S when chunk is
         P.n0 = f0;
         e = cnn_forward(C, P, nf, 1, H, W, seq + f0 * per, per, 0, out + f0 * per, s);
         if (e != hipSuccess) return e;
