@@ -561,27 +561,44 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs A)
     if (g == 0) out[TAPS * CH * CH + r] = bsum;
 }
 
-// grad_flat[layer] <- sum of the per-wave partials (fixed order), real channels
-// and parameter taps only
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwaves, int layer, const NetShape S,
-                               float *__restrict__ grad)
+// grad_flat[layer] <- sum of the per-wave partials, real channels and
+// parameter taps only.  A workgroup takes 16 elements; 16 thread groups split
+// the partial list into contiguous sixteenths, each thread keeping 8 running
+// sums (loads in flight), and the groups are added in order through LDS: a
+// fixed summation order, so the gradient is deterministic.
+constexpr int WG_RGROUPS = 16;
+static_assert((WG_BLOCKS * 4) % (WG_RGROUPS * 8) == 0, "partials split evenly");
+
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part, int nwaves, int layer,
+                                                      const NetShape S, float *__restrict__ grad)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= PART) return;
+    __shared__ float red[WG_RGROUPS][17];
+    const int el = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + el;
+    float acc8[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (e < PART) {
+        const int per = nwaves / WG_RGROUPS;
+        const float *p = part + (int64_t)grp * per * PART + e;
+        for (int w = 0; w < per; w += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc8[u] += p[(int64_t)(w + u) * PART];
+        }
+    }
+    red[grp][el] = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+    __syncthreads();
+    if (grp != 0 || e >= PART) return;
+    float sum = 0.0f;
+    for (int q = 0; q < WG_RGROUPS; ++q) sum += red[q][el];
     const int cin = net_cin(S, layer), cout = COUT[layer];
     if (e < TAPS * CH * CH) {
         const int tap = e / (CH * CH), o = (e / CH) % CH, i = e % CH;
         const int pt = net_ptap(S, tap);
         if (o >= cout || i >= cin || pt < 0) return;
-        float s = 0.0f;
-        for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * PART + e];
-        grad[S.poff[layer] + (o * cin + i) * S.ptaps + pt] = s;
+        grad[S.poff[layer] + (o * cin + i) * S.ptaps + pt] = sum;
     } else {
         const int o = e - TAPS * CH * CH;
         if (o >= cout) return;
-        float s = 0.0f;
-        for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * PART + e];
-        grad[S.poff[layer] + cout * cin * S.ptaps + o] = s;
+        grad[S.poff[layer] + cout * cin * S.ptaps + o] = sum;
     }
 }
 
@@ -1147,7 +1164,7 @@ msf_status msf_cnn_train_step(msf_cnn *C, const float *v, const float *g, const 
         WgradArgs W{gcur, C->h[l], n, nz, ny, nx, C->part};
         hipLaunchKernelGGL(k_wgrad, dim3(WG_BLOCKS), dim3(256), 0, s, W);
         CHK(hipGetLastError());
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((PART + 255) / 256), dim3(256), 0, s, C->part, WG_BLOCKS * 4, l,
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((PART + 15) / 16), dim3(256), 0, s, C->part, WG_BLOCKS * 4, l,
                            C->shape, C->grad);
         CHK(hipGetLastError());
         if (l > 0) {
