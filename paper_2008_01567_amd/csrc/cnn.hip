@@ -263,6 +263,10 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
     int64_t t = blockIdx.x;
     if (t >= ntile) return;                  // the whole workgroup
     TilePos p = tile_pos(t, ntx, nty);
+    __syncthreads();                         // the weights are staged
+    v4s wr[9];                               // this lane's weight blocks, in registers
+#pragma unroll
+    for (int q = 0; q < 9; ++q) wr[q] = wl[q * (CH * 4) + r * 4 + g];
     uint4 reg[F32IN ? 1 : TILE_LD];
     float regf[F32IN ? TILE_VLD : 1][5];
     if constexpr (F32IN) tile_fetch_f32(A, p, regf);
@@ -297,8 +301,7 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
                 for (int dx = 0; dx < 3; ++dx) {
                     // staged voxel (row ry + dy, column 16 wave + r + dx), channels 4g .. 4g + 3
                     const v4s a = tl[((ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[(dy * 3 + dx) * (CH * 4) + r * 4 + g], a, acc,
-                                                                    0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[dy * 3 + dx], a, acc, 0, 0, 0);
                 }
             const int y = pc.y0 + ry, xv = xs + r;
             if (xv < A.X)
@@ -349,6 +352,10 @@ __global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int 
     const int si = (int)(b / nty);
     const float4 bias = conv_bias(A, g);
     const int xs = x0 + 16 * wave;
+    __syncthreads();                         // the weights are staged
+    v4s wr[9];                               // this lane's weight blocks, in registers
+#pragma unroll
+    for (int q = 0; q < 9; ++q) wr[q] = wl[q * (CH * 4) + r * 4 + g];
     float reg[RING_LD];
     auto stage = [&](int f) {
 #pragma unroll
@@ -385,8 +392,7 @@ __global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int 
                         v4s a;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) a[j] = sb[j] >= 0 ? (short)ring[sb[j] + o] : (short)0;
-                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[(dy * 3 + dx) * (CH * 4) + r * 4 + g], a,
-                                                                        acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[dy * 3 + dx], a, acc, 0, 0, 0);
                     }
                 const int y = y0 + ry, xv = xs + r;
                 if (xv < A.X) conv_store<EPI_RELU>(A, acc, bias, (n * A.Y + y) * A.X + xv, 0, g);
@@ -443,6 +449,11 @@ __global__ __launch_bounds__(256) void k_conv3d(const ConvArgs A)
     const int xs = x0 + 16 * wave;           // this wave's segment
     // ring slot of slice z (z >= zbeg - 1)
     auto slot = [&](int z) { return (z - zbeg + 1) % 3; };
+    __syncthreads();                         // the weights are staged
+    // this lane's weight blocks stay in registers (LDS then serves only the activations)
+    v4s wr[TAPS];
+#pragma unroll
+    for (int q = 0; q < TAPS; ++q) wr[q] = wl[q * (CH * 4) + r * 4 + g];
     uint4 reg[SL_LD];
     slice_fetch(A, n, zbeg - 1, y0, x0, reg);
 #pragma unroll
@@ -478,8 +489,7 @@ __global__ __launch_bounds__(256) void k_conv3d(const ConvArgs A)
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
                         const v4s a = tl[(sb + (ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
-                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                            wl[((dz * 3 + dy) * 3 + dx) * (CH * 4) + r * 4 + g], a, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[(dz * 3 + dy) * 3 + dx], a, acc, 0, 0, 0);
                     }
             }
             const int y = y0 + ry, xv = xs + r;
