@@ -1127,7 +1127,8 @@ msf_status msf_denoise25(msf_cnn *C, const float *w, int32_t n_frames, int32_t n
         return MSF_EINVAL;
     }
     const int64_t n = (int64_t)n_frames * nz * ny * nx;
-    if (w < out + n && out < w + n) { set_error("msf_denoise25: out overlaps w"); return MSF_EINVAL; }
+    const uintptr_t wb = (uintptr_t)w, ob = (uintptr_t)out, bytes = (uintptr_t)n * sizeof(float);
+    if (wb < ob + bytes && ob < wb + bytes) { set_error("msf_denoise25: out overlaps w"); return MSF_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     float *sa = nullptr, *sb = nullptr;
     if (plane != 1) {
