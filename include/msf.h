@@ -185,8 +185,8 @@ msf_status msf_prox_features(msf_plan *plan, const float *v, const float *y, con
 /* ---- the two networks (BF16 weights and activations on the matrix cores,
  * FP32 accumulation, FP32 master parameters; zero "same" padding) ----
  *
- * MSF_CNN_WARM_START (msf_cnn_create; not from the paper, plain CG stays the
- * judge of its prediction): 3D CNN, 3x3x3 kernels, channels 2 -> 16 -> 16 ->
+ * MSF_CNN_WARM_START (msf_cnn_create; not from the paper, plain CG decides
+ * whether its prediction is kept): 3D CNN, 3x3x3 kernels, channels 2 -> 16 -> 16 ->
  * 16 -> 1, ReLU after the first three layers,
  *     x0 = v + c_o * f(v / c_v, g / c_g)
  * with g the feature above and scales (c_v, c_g, c_o).  15169 parameters:

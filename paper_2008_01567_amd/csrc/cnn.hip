@@ -5,7 +5,7 @@
 // three layers) predicting x0 = v + c_o f(v / c_v, g / c_g), where g is the
 // data term's backprojected weighted residual at v in voxel units and c_v,
 // c_g, c_o are fixed scales stored with the network.  The paper has no such
-// network; plain CG remains the fallback and the judge of the prediction.
+// network; plain CG remains the fallback and decides whether the prediction is kept.
 //
 // The 2.5D denoiser of the multi-slice fusion prior agents (paper Sec. IV):
 // the same four layers as a 2D network (3x3 kernels, channels 5 -> 16 -> 16
