@@ -248,7 +248,7 @@ __device__ __forceinline__ Pieces ray_pieces_open(const RayZ &z, float scur, flo
     // cross ? max(szn, scur) : snext, as one median (scur <= snext along the walk)
     const float mid = __builtin_amdgcn_fmed3f(z.szn, scur, snext);
     q.l1 = mid - scur;
-    q.l2 = q.cross ? snext - mid : 0.0f;
+    q.l2 = snext - mid;     // exactly 0 without a crossing (mid = snext)
     q.iz = z.iz;
     q.iz2 = z.iz + (q.cross ? z.zstep : 0);
     return q;
