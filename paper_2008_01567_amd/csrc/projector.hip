@@ -163,6 +163,12 @@ struct RayZ {
     float lzi, lzo;     // s-range inside the z slab of the volume
     float szn;          // next z-plane crossing
     int iz, zstep;
+    // open walk: kd = index of the next plane minus nz/2 (an exact double),
+    // nsf = -sf (+inf for a ray that crosses no plane, so szn stays +inf), the
+    // voxel's byte offset in the column and its step, and the high word of
+    // the step as a double (the low word of +-1.0 is 0)
+    double kd, nsf;
+    int izb, zstepb, zsd_hi;
 };
 
 // OPEN: the ray's z slab index is not clamped to the volume.  Outside [0, nz)
@@ -196,7 +202,14 @@ __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, 
         z.lzo = -INFINITY;
         z.iz = OPEN ? -(1 << 24) : 0;   // open walk: far outside, never crossing back in
         z.szn = INFINITY;
-        if (OPEN) z.zstep = 0;
+        if (OPEN) {
+            z.zstep = 0;
+            z.izb = z.iz * 4;
+            z.zstepb = 0;
+            z.zsd_hi = 0;
+            z.kd = 0.0;
+            z.nsf = INFINITY;
+        }
         return;
     }
     z.lzi = (float)lzi;
@@ -205,6 +218,13 @@ __device__ __forceinline__ void ray_setup(const ProjParams &P, const Column &c, 
     else if (lzi >= c.s_in) z.iz = z.zstep > 0 ? 0 : P.nz - 1;
     else z.iz = min(max((int)floor(z_in + hz), 0), P.nz - 1);
     z.szn = z.zstep ? (float)zplane_s(z.iz + (z.zstep > 0), hz, z.im, z.sf) : INFINITY;
+    if (OPEN) {
+        z.izb = z.iz * 4;
+        z.zstepb = z.zstep * 4;
+        z.zsd_hi = z.zstep > 0 ? 0x3FF00000 : (z.zstep < 0 ? (int)0xBFF00000u : 0);
+        z.kd = (double)(z.iz + (z.zstep > 0)) - hz;   // exact: an integer or half-integer
+        z.nsf = z.zstep ? -z.sf : INFINITY;            // then fma(kd, im, nsf) is szn
+    }
 }
 
 // One ray inside the xy cell [scur, snext] when at most one z plane can be
@@ -240,18 +260,35 @@ __device__ __forceinline__ void ray_advance(RayZ &z, const Pieces &q, double hz)
 }
 
 // Open walk (see ray_setup<true>): the pieces of the cell [scur, snext] on
-// both sides of at most one z crossing, with no clipping to the volume.
-__device__ __forceinline__ Pieces ray_pieces_open(const RayZ &z, float scur, float snext)
+// both sides of at most one z crossing, with no clipping to the volume; the
+// voxels as byte offsets in the column.
+struct PiecesOpen {
+    int ob1, ob2;
+    float l1, l2;
+    bool cross;
+};
+
+__device__ __forceinline__ PiecesOpen ray_pieces_open(const RayZ &z, float scur, float snext)
 {
-    Pieces q;
+    PiecesOpen q;
     q.cross = z.szn < snext;
     // cross ? max(szn, scur) : snext, as one median (scur <= snext along the walk)
     const float mid = __builtin_amdgcn_fmed3f(z.szn, scur, snext);
     q.l1 = mid - scur;
     q.l2 = snext - mid;     // exactly 0 without a crossing (mid = snext)
-    q.iz = z.iz;
-    q.iz2 = z.iz + (q.cross ? z.zstep : 0);
+    q.ob1 = z.izb;
+    q.ob2 = z.izb + (q.cross ? z.zstepb : 0);
     return q;
+}
+
+// After a crossing the next plane is one step on; szn is recomputed from kd
+// either way (without a crossing that gives the same value), with the same
+// rounded expression as zplane_s since kd equals (double)k - nz/2 exactly.
+__device__ __forceinline__ void ray_advance_open(RayZ &z, const PiecesOpen &q)
+{
+    z.kd += __hiloint2double(q.cross ? z.zsd_hi : 0, 0);
+    z.szn = (float)fma(z.kd, z.im, z.nsf);
+    z.izb = q.ob2;
 }
 
 // General case (steep rays): walk every z crossing inside the cell.
@@ -470,7 +507,7 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
                 }
                 if (MODE != PM_COUNT && !STEEP) {
                     // all pieces first, then all 2R loads, then the sums: one wait per cell
-                    Pieces q[R];
+                    PiecesOpen q[R];
                     float p1[R], p2[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) q[r] = ray_pieces_open(z[r], scur, snext);
@@ -478,13 +515,13 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
                     const __amdgpu_buffer_rsrc_t colr = row_rsrc(colp, P.nz * 4);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        p1[r] = row_f32(colr, q[r].iz);
-                        p2[r] = row_f32(colr, q[r].iz2);
+                        p1[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(colr, q[r].ob1, 0, 0));
+                        p2[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(colr, q[r].ob2, 0, 0));
                     }
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         acc32[r] = fmaf(q[r].l2, p2[r], fmaf(q[r].l1, p1[r], acc32[r]));
-                        ray_advance(z[r], q[r], 0.5 * P.nz);
+                        ray_advance_open(z[r], q[r]);
                     }
                 }
             };
