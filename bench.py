@@ -38,9 +38,9 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "c11831f1f3283598c1b0caf232b7419f2096342eff93d3d068e4ad7a7382e6b2",
+    "source_sha256": "a7a366e5f68167c9b23fa0afa5b8c56da1d6c3a286bad958cca53bbdc11f96cb",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
-    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.5e6,
+    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.6e6,
     "read_bytes": 987.6e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.932,
     # SQ_INSTS_VALU x 64 / nnz(A) of the same runs: VALU lane-instructions per intersection
     "valu_lane_instr_per_intersection": 31.6,
