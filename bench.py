@@ -2,7 +2,7 @@
 """Benchmark of the batched forward-model proximal map on one MI355X.
 
 One step = one call of the whole hot path on one batch: the proximal map of
-the data term (paper eq. (mace_L)) for all 16 frames of the 128^3 x 16
+the data term (paper eq. (4)) for all 16 frames of the 128^3 x 16
 workload (192^2 detector, 16 interlaced views per frame over 360 degrees),
 solved by the HIP library's batched CG to the frozen stopping rule, started
 from the trained network's prediction (learned + batched; the network's

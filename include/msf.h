@@ -4,13 +4,13 @@
  * Sparse-View and Limited-Angle 4D CT Reconstruction"), built for MI355X
  * (gfx950).
  *
- * The operation (paper Sec. II, eqs. (LL_time_expand) and Sec. III,
- * eq. (mace_L)): for each time frame n,
+ * The operation (paper Sec. II, eq. (2), and Sec. III,
+ * eq. (4)): for each time frame n,
  *
  *     x_n = argmin_z  1/2 || y_n - A_n z ||^2_{Lambda_n} + || v_n - z ||^2 / (2 sigma^2)
  *
  * which is the solution of (A_n^T Lambda_n A_n + sigma^-2 I) z = A_n^T Lambda_n y_n + sigma^-2 v_n.
- * The data term is separable over time frames (eq. (LL_time_expand)), so every
+ * The data term is separable over time frames (eq. (2)), so every
  * frame is an independent problem; the library solves all of them in one
  * batch.  A_n is the cone-beam system matrix: A_n[i][j] is the length of the
  * segment from the point source to the centre of detector pixel i inside
@@ -156,7 +156,7 @@ msf_status msf_plan_autotune(msf_plan *plan, const char *cache_path, msf_tiles *
 msf_status msf_plan_sizes(const msf_plan *plan, int64_t *n_vox_total, int64_t *n_meas_total,
                           int64_t *workspace_bytes);
 
-/* y = A x for every frame (paper eq. (LL_time_expand)).  x: device volume
+/* y = A x for every frame (paper eq. (2)).  x: device volume
  * [n_frames][nz][ny][nx]; y: device sinogram (all views), overwritten. */
 msf_status msf_project(msf_plan *plan, const float *x, float *y, void *stream);
 
@@ -164,7 +164,7 @@ msf_status msf_project(msf_plan *plan, const float *x, float *y, void *stream);
  * y: device sinogram; x: device volume, overwritten. */
 msf_status msf_backproject(msf_plan *plan, const float *y, float *x, void *stream);
 
-/* The proximal map of the data term (paper eq. (mace_L)) for every frame, by
+/* The proximal map of the data term (paper eq. (4)) for every frame, by
  * conjugate gradients batched over frames: FP32 vectors, FP64 step sizes,
  * inner products and residual norms.  v: device volume; y, lambda: device
  * sinograms (lambda >= 0 and finite, else EINVAL); sigma > 0; x_out: device
@@ -247,7 +247,7 @@ msf_status msf_denoise25(msf_cnn *cnn, const float *w, int32_t n_frames, int32_t
  * Algorithm 1 of the paper (partial-update Mann iteration, Sec. III):
  *     X <- F~(W; X);  Z <- G(2X - W);  W <- W + 2 rho (Z - X);  output X_0,
  * with F~ = [L~(W_0; X_0), H_1(W_1), H_2(W_2), H_3(W_3)] and G the weighted
- * average W_0/(1+beta) + beta/(1+beta) mean_k W_k (eqs. (mace_G), (mace_avg)).
+ * average W_0/(1+beta) + beta/(1+beta) mean_k W_k (eqs. (8), (9)).
  * L~ is msf_prox_solve on W_0 started from the previous X_0: to tol (full
  * proximal map, partial_iters = 0) or for partial_iters CG steps (the paper's
  * partial update).  Prior agents: MSF_PRIOR_CNN = the paper's multi-slice

@@ -9,9 +9,9 @@ method's arithmetic.
 Contents
 --------
 * ``FrameMatrix``: the system matrix A_n of one time frame (paper eq.
-  (LL_time_expand)) as an FP64 CSR matrix of exact ray-voxel lengths, built by
+  (2)) as an FP64 CSR matrix of exact ray-voxel lengths, built by
   Siddon's method or by brute force (see ``oracle.c``), its transpose, and
-  the FP64 conjugate-gradient solve of the proximal map (eq. (mace_L)).
+  the FP64 conjugate-gradient solve of the proximal map (eq. (4)).
 * ``prox_dense``: the proximal map as the dense normal-equation solve
   (Cholesky), for volumes up to 16^3.
 * ``oracle.cnn``: FP64 3D convolutional network forward/backward and Adam.

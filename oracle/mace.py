@@ -1,7 +1,7 @@
 """FP64 oracle of the MACE outer loop (TEST INFRASTRUCTURE ONLY).
 
-Paper Sec. III: agents F = [L(W_0); H_1(W_1); ...; H_K(W_K)] (eq. (mace_F)),
-the averaging operator G (eqs. (mace_G), (mace_avg)) with weight beta, and
+Paper Sec. III: agents F = [L(W_0); H_1(W_1); ...; H_K(W_K)] (eq. (6)),
+the averaging operator G (eqs. (8), (9)) with weight beta, and
 Algorithm 1 (partial-update Mann iteration):  starting from X = W = copies of
 x^(0), repeat  X <- F~(W; X),  Z <- G(2X - W),  W <- W + 2 rho (Z - X);
 the reconstruction is X_0.
@@ -12,13 +12,13 @@ import numpy as np
 
 
 def weighted_mean(W, beta: float):
-    """eq. (mace_avg): W_0/(1+beta) + beta/(1+beta) * mean_k W_k."""
+    """eq. (9): W_0/(1+beta) + beta/(1+beta) * mean_k W_k."""
     K = len(W) - 1
     return W[0] / (1.0 + beta) + (beta / (1.0 + beta)) * (sum(W[1:]) / K)
 
 
 def G(W, beta: float):
-    """eq. (mace_G): every component replaced by the weighted mean."""
+    """eq. (8): every component replaced by the weighted mean."""
     m = weighted_mean(W, beta)
     return [m.copy() for _ in W]
 

@@ -5,8 +5,8 @@
  * benchmark's CPU-baseline leg may load this library.  It shares no code
  * with the HIP library: it is plain, slow and written to be checked by eye.
  *
- * What it computes (paper Sec. II, eq. (LL_time_expand), and Sec. III,
- * eq. (mace_L)):  for every time frame n the data term is
+ * What it computes (paper Sec. II, eq. (2), and Sec. III,
+ * eq. (4)):  for every time frame n the data term is
  *     l_n(x) = 1/2 || y_n - A_n x ||^2_{Lambda_n}
  * and the proximal map of the data term is the minimiser of
  *     l_n(z) + ||x - z||^2 / (2 sigma^2),

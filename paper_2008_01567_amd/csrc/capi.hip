@@ -1,6 +1,6 @@
 // Host side of the C ABI declared in include/msf.h: argument validation,
 // plan/workspace management, layout conversion at the boundary, and the
-// batched CG driver of the proximal map (paper Sec. III, eq. (mace_L)).
+// batched CG driver of the proximal map (paper Sec. III, eq. (4)).
 #include "msf_internal.h"
 
 #include <algorithm>

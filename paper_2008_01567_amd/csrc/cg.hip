@@ -1,6 +1,6 @@
 // Batched conjugate gradients for the proximal map of the data term
-// (paper Sec. III, eq. (mace_L)), one independent system per time frame
-// (the data term separates over frames, eq. (LL_time_expand)):
+// (paper Sec. III, eq. (4)), one independent system per time frame
+// (the data term separates over frames, eq. (2)):
 //     H_n = A_n^T Lambda_n A_n + sigma^-2 I,   b_n = A_n^T Lambda_n y_n + sigma^-2 v_n.
 // Vectors are FP32 in HBM; every inner product, step size and residual norm
 // is FP64.  Vector updates are evaluated in FP64 and rounded once to FP32.

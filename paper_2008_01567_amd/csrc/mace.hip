@@ -1,8 +1,8 @@
 // Multi-agent consensus equilibrium (paper Sec. III) around the batched
 // proximal map: Algorithm 1, the partial-update Mann iteration
 //     X <- F~(W; X);   Z <- G(2X - W);   W <- W + 2 rho (Z - X),
-// with F~ = [L~(W_0; X_0), H_1(W_1), ..., H_K(W_K)] (eq. (L_tilde_operator)),
-// G the weighted averaging of eqs. (mace_G), (mace_avg), and the output X_0.
+// with F~ = [L~(W_0; X_0), H_1(W_1), ..., H_K(W_K)] (eq. (13)),
+// G the weighted averaging of eqs. (8), (9), and the output X_0.
 //
 // L~ is msf_prox_solve on W_0 started from the previous X_0: to the tolerance
 // (full proximal map) or for a fixed number of CG steps (the partial update

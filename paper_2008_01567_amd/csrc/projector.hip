@@ -1,7 +1,7 @@
 // Cone-beam forward projector A and its adjoint A^T for gfx950.
 //
 // A[i][j] is the length of ray i (point source -> detector pixel centre)
-// inside voxel j (paper Sec. II: the system matrix of eq. (LL_time_expand);
+// inside voxel j (paper Sec. II: the system matrix of eq. (2);
 // the exact ray-voxel length is this library's discretisation of it).  The
 // lengths are computed on the fly by a Siddon-type traversal (Siddon 1985):
 // the ray is cut at every voxel-plane crossing and each piece is credited to

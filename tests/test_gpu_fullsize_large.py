@@ -8,7 +8,7 @@ build the system matrix (10^8-10^9 nonzeros per frame):
 
 The oracle checks what it can compute one by one: sampled rays of A, sampled
 voxels of A^T, and sampled components of the FP64 gradient of the proximal
-objective (paper eq. (mace_L)) at the GPU's solution, which must vanish to the
+objective (paper eq. (4)) at the GPU's solution, which must vanish to the
 FP32 resolution of x.  The measurement y is the analytic projection of the
 continuous phantom plus the workloads' noise (the oracle's projector would
 need the whole matrix).  Relative-error parity against a full FP64 solve is
@@ -139,7 +139,7 @@ def test_c5_mace_data_agent_optimality(c5):
 
 def test_c5_mace_partial_updates(c5):
     """The workload's MACE run at full size: 10 outer iterations, partial data-agent updates
-    of 20 CG steps per frame (eq. (L_tilde_operator)), plane-wise smoother agents, rho 0.5,
+    of 20 CG steps per frame (eq. (13)), plane-wise smoother agents, rho 0.5,
     beta 1 (about 40 s on one MI355X)."""
     msf, cfg, g, x0, v, y, lam, plan, dev = c5
     x, st = plan.mace(dev["y"], dev["lam"], cfg.sigma, x_init=dev["v"], n_iter=10, partial_iters=20)

@@ -1,6 +1,6 @@
 """Pins of the FP64 MACE oracle (paper Sec. III): the averaging identities and
 the consensus equilibrium of proximal agents, which solves the multi-regularised
-MAP problem of eq. (map_multireg)."""
+MAP problem of eq. (3)."""
 import numpy as np
 
 import oracle

@@ -1,4 +1,4 @@
-"""Pins of the FP64 oracle projector (system matrix of paper eq. (LL_time_expand)).
+"""Pins of the FP64 oracle projector (system matrix of paper eq. (2)).
 
 The oracle is checked against things other than itself: brute-force clipping
 of every voxel, hand-derived lengths (tests/golden), the chord through the

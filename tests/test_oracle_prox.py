@@ -1,4 +1,4 @@
-"""Pins of the FP64 proximal-map oracle (paper eq. (mace_L) with the data term of eq. (LL_time_expand)).
+"""Pins of the FP64 proximal-map oracle (paper eq. (4) with the data term of eq. (2)).
 
 The CG oracle is checked against the dense normal-equation solve, closed-form
 special cases, linearity, the first-order small-sigma expansion and the
