@@ -127,7 +127,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU; the proximal map shards by frame across GPUs "
+        print("bench.py: the library runs on one GPU; the proximal map shards by frame across GPUs "
               "(design only), so --gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
