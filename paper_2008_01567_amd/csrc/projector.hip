@@ -398,34 +398,53 @@ __device__ __forceinline__ void walk_xy(const ProjParams &P, const Column &c, Bo
 // The same walk read from the column's precomputed table (bit-identical
 // cells and parameters); the entries of the next 8 cells are loaded while the
 // current ones are processed.
-template <class Body, class Flush>
+//
+// PAD: the body adds nothing for an empty cell [s, s] (every piece has length
+// 0 and the walk state stays valid), so a block of 8 cells is processed
+// whole, the cells past the end repeating the last one with zero length.
+// With no branch between its cells a block is one straight run of code, and
+// the loads of later cells can be issued before the sums of earlier ones.
+// The flush still comes after every FLUSH (= 2 blocks) cells, as without PAD.
+template <bool PAD = false, class Body, class Flush>
 __device__ __forceinline__ void walk_table(const ProjParams &P, int64_t col, Body &&body, Flush &&flush)
 {
     const WalkHead h = P.walk_head[col];
     const WalkEntry *e = P.walk_ent + col * P.walk_stride;
     constexpr int B = 8;
+    static_assert(!PAD || FLUSH == 2 * B, "PAD flushes every second block");
     float scur = h.s_in;
     int k = 0;
+    // PAD reads past the walk's end as its last entry; an empty walk runs no block
+    const int last = PAD ? max(h.n - 1, 0) : P.walk_stride - 1;
     WalkEntry next[B];
 #pragma unroll
-    for (int j = 0; j < B; ++j) next[j] = e[min(j, P.walk_stride - 1)];
+    for (int j = 0; j < B; ++j) next[j] = e[min(j, last)];
     for (int c0 = 0; c0 < h.n; c0 += B) {
         WalkEntry cur[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) cur[j] = next[j];
         if (c0 + B < h.n) {
 #pragma unroll
-            for (int j = 0; j < B; ++j) next[j] = e[min(c0 + B + j, P.walk_stride - 1)];
+            for (int j = 0; j < B; ++j) next[j] = e[min(c0 + B + j, last)];
         }
+        if (PAD) {
 #pragma unroll
-        for (int j = 0; j < B; ++j) {
-            if (c0 + j >= h.n) break;
-            body((int64_t)cur[j].cell * P.nz, scur, cur[j].snext);
-            if (++k == FLUSH) {
-                flush();
-                k = 0;
+            for (int j = 0; j < B; ++j) {
+                body((int64_t)cur[j].cell * P.nz, scur, cur[j].snext);
+                scur = cur[j].snext;
             }
-            scur = cur[j].snext;
+            if (c0 & B) flush();
+        } else {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                if (c0 + j >= h.n) break;
+                body((int64_t)cur[j].cell * P.nz, scur, cur[j].snext);
+                if (++k == FLUSH) {
+                    flush();
+                    k = 0;
+                }
+                scur = cur[j].snext;
+            }
         }
     }
     flush();
@@ -525,7 +544,7 @@ __global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float
                     }
                 }
             };
-            if (WT) walk_table(P, (int64_t)T.view * P.nu + T.iu, cell_body, flush);
+            if (WT) walk_table<MODE != PM_COUNT && !STEEP>(P, (int64_t)T.view * P.nu + T.iu, cell_body, flush);
             else walk_xy(P, c, cell_body, flush);
         }
         const int64_t base = (int64_t)T.view * P.nu * P.nv + (int64_t)T.iu * P.nv;
