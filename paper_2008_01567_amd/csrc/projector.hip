@@ -764,60 +764,85 @@ __global__ void k_cell_table(const ProjParams P, int64_t n_views, int32_t *__res
 
 // The voxels of one lane (z = iz[k]) against column iu's piece [fa, fb]:
 // add length * pre-scaled sinogram value of every detector row whose ray
-// passes through the voxel inside the piece.  All row indices first, then all
-// loads, then the arithmetic: one wait for the whole column.
+// passes through the voxel inside the piece.  In two phases, so that a caller
+// can issue the loads of several columns before their arithmetic:
+// column_load finds every voxel's first candidate row and loads the first
+// two candidates, column_sum takes the lengths (and reads any further rows).
 template <int ZPL>
-__device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino_v, int iu, double sf,
-                                              float fa, float fb, float ka, float kb, const int (&iz)[ZPL],
-                                              const double (&klo)[ZPL], float (&vacc)[ZPL])
+struct ColumnRows {
+    __amdgpu_buffer_rsrc_t srow, irow;   // the column's sinogram values and crossing slopes
+    int iva[ZPL];
+    double ima[ZPL], imb[ZPL];
+    float sva[ZPL], svb[ZPL];
+};
+
+template <int ZPL>
+__device__ __forceinline__ void column_load(const ProjParams &P, const float *sino_v, int iu, float ka, float kb,
+                                            const int (&iz)[ZPL], ColumnRows<ZPL> &C)
 {
     const float hzf = 0.5f * P.nz;
     // detector row coordinate of height zp: zp * inv_dv + (cv - offv * inv_dv), widened by 1e-3 row
     const float inv_dv = (float)(1.0 / P.dv);
-    const float c0 = (float)(0.5 * (P.nv - 1) - P.offv / P.dv);
-    const float c_lo = c0 - 1e-3f, c_hi = c0 + 1e-3f;
+    const float c_lo = (float)(0.5 * (P.nv - 1) - P.offv / P.dv) - 1e-3f;
     // sino_v: the view's sinogram; nu * nv < 2^31, so the column offset is 32-bit
     const int coff = iu * P.nv;
-    const __amdgpu_buffer_rsrc_t srow = row_rsrc(sino_v + coff, P.nv * 4);
-    const __amdgpu_buffer_rsrc_t irow = row_rsrc(P.imtab + coff, P.nv * 8);
-    int iva[ZPL];
+    C.srow = row_rsrc(sino_v + coff, P.nv * 4);
+    C.irow = row_rsrc(P.imtab + coff, P.nv * 8);
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         // rows through [zlo, zhi] within [fa, fb]: zp between z * ka and z * kb
         const float zlo = iz[k] - hzf;
         const float zp_lo = fminf(zlo * ka, zlo * kb);
-        iva[k] = max((int)ceilf(fmaf(zp_lo, inv_dv, c_lo)), P.iv_lo);
+        C.iva[k] = max((int)ceilf(fmaf(zp_lo, inv_dv, c_lo)), P.iv_lo);
     }
     // the first two candidate rows of every voxel without a branch.  Reads past a
     // row give 0, and a row outside [iva, ivb] misses the voxel inside the piece, so
     // its length is <= 0 and adds nothing once clamped at 0.  (Lanes past nz are
     // never written back.)
-    double ima[ZPL], imb[ZPL];
-    float sva[ZPL], svb[ZPL];
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
-        ima[k] = row_f64(irow, iva[k]);
-        imb[k] = row_f64_next(irow, iva[k]);
-        sva[k] = row_f32(srow, iva[k]);
-        svb[k] = row_f32_next(srow, iva[k]);
+        C.ima[k] = row_f64(C.irow, C.iva[k]);
+        C.imb[k] = row_f64_next(C.irow, C.iva[k]);
+        C.sva[k] = row_f32(C.srow, C.iva[k]);
+        C.svb[k] = row_f32_next(C.srow, C.iva[k]);
     }
+}
+
+template <int ZPL>
+__device__ __forceinline__ void column_sum(const ProjParams &P, const ColumnRows<ZPL> &C, double sf, float fa,
+                                           float fb, float ka, float kb, const int (&iz)[ZPL],
+                                           const double (&klo)[ZPL], float (&vacc)[ZPL])
+{
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
-        const float la = fmaxf(slab_piece(ima[k], sf, klo[k], fa, fb), 0.0f);
-        const float lb = fmaxf(slab_piece(imb[k], sf, klo[k], fa, fb), 0.0f);
-        float acc_k = fmaf(lb, svb[k], fmaf(la, sva[k], vacc[k]));
+        const float la = fmaxf(slab_piece(C.ima[k], sf, klo[k], fa, fb), 0.0f);
+        const float lb = fmaxf(slab_piece(C.imb[k], sf, klo[k], fa, fb), 0.0f);
+        float acc_k = fmaf(lb, C.svb[k], fmaf(la, C.sva[k], vacc[k]));
         if (P.multi_row) {
             // geometries where a ray can meet a voxel in three or more rows: the further candidates
+            const float hzf = 0.5f * P.nz;
+            const float inv_dv = (float)(1.0 / P.dv);
+            const float c_hi = (float)(0.5 * (P.nv - 1) - P.offv / P.dv) + 1e-3f;
             const float zlo = iz[k] - hzf;
             const float zp_hi = fmaxf(fmaf(zlo, ka, ka), fmaf(zlo, kb, kb));
             const int ivb = min((int)floorf(fmaf(zp_hi, inv_dv, c_hi)), P.iv_hi);
-            for (int ivr = iva[k] + 2; ivr <= ivb; ++ivr) {
-                const float l = slab_piece(row_f64(irow, ivr), sf, klo[k], fa, fb);
-                if (l > 0.0f) acc_k = fmaf(l, row_f32(srow, ivr), acc_k);
+            for (int ivr = C.iva[k] + 2; ivr <= ivb; ++ivr) {
+                const float l = slab_piece(row_f64(C.irow, ivr), sf, klo[k], fa, fb);
+                if (l > 0.0f) acc_k = fmaf(l, row_f32(C.srow, ivr), acc_k);
             }
         }
         vacc[k] = acc_k;
     }
+}
+
+template <int ZPL>
+__device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino_v, int iu, double sf,
+                                              float fa, float fb, float ka, float kb, const int (&iz)[ZPL],
+                                              const double (&klo)[ZPL], float (&vacc)[ZPL])
+{
+    ColumnRows<ZPL> C;
+    column_load<ZPL>(P, sino_v, iu, ka, kb, iz, C);
+    column_sum<ZPL>(P, C, sf, fa, fb, ka, kb, iz, klo, vacc);
 }
 
 // KT = 0: the pieces are computed on the fly (back_mode 1); KT = 2, 3: they
@@ -859,36 +884,73 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
         const int32_t *hdr = P.cell_hdr + v0 * ncell + cell;
         const CellEntry *ent = P.cell_ent + (v0 * ncell + cell) * KT;
         const float *sino_v = sino + v0 * view_len;
-        int n_next = 0;
-        CellEntry e_next[KT];
+        // Views go in pairs (a, b).  The first slot of a view is processed
+        // without a branch: when no column meets the cell it holds a zero
+        // piece (fa = fb = 0), whose lengths are exactly 0, and so does the
+        // missing b of an odd last pair (reading view a's sinogram).  Both
+        // first slots' rows are loaded before either view's sums are taken.
+        // Each view keeps its own FP32 sum, and they enter the FP64 sum in
+        // view order, as one view at a time would.
+        const CellEntry zero{0.0f, 0.0f, 0.0f, 0.0f, 0.0, 0, 0};
+        int na_next = 0, nb_next = 0;
+        CellEntry ea_next = zero, eb_next = zero;
         if (v0 < v1) {
-            n_next = *hdr;
-#pragma unroll
-            for (int j = 0; j < KT; ++j) e_next[j] = ent[j];
+            na_next = hdr[0];
+            ea_next = ent[0];
         }
-        for (int64_t v = v0; v < v1; ++v, sino_v += view_len) {
-            const int n = n_next;
-            CellEntry ec[KT];
-#pragma unroll
-            for (int j = 0; j < KT; ++j) ec[j] = e_next[j];
-            if (v + 1 < v1) {
-                hdr += ncell;
-                ent += ncell * KT;
-                n_next = *hdr;
-#pragma unroll
-                for (int j = 0; j < KT; ++j) e_next[j] = ent[j];
+        if (v0 + 1 < v1) {
+            nb_next = hdr[ncell];
+            eb_next = ent[ncell * KT];
+        }
+        for (int64_t v = v0; v < v1; v += 2, sino_v += 2 * view_len) {
+            const bool has_b = v + 1 < v1;
+            const int na = na_next, nb = nb_next;
+            const CellEntry ea = ea_next, eb = eb_next;
+            const CellEntry *ent_a = ent, *ent_b = ent + ncell * KT;
+            hdr += 2 * ncell;
+            ent += 2 * ncell * KT;
+            na_next = 0;
+            nb_next = 0;
+            ea_next = zero;
+            eb_next = zero;
+            if (v + 2 < v1) {
+                na_next = hdr[0];
+                ea_next = ent[0];
             }
-            float vacc[ZPL];
+            if (v + 3 < v1) {
+                nb_next = hdr[ncell];
+                eb_next = ent[ncell * KT];
+            }
+            const float *sino_b = has_b ? sino_v + view_len : sino_v;
+            float va[ZPL], vb[ZPL];
 #pragma unroll
-            for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
+            for (int k = 0; k < ZPL; ++k) {
+                va[k] = 0.0f;
+                vb[k] = 0.0f;
+            }
+            ColumnRows<ZPL> ca, cb;
+            column_load<ZPL>(P, sino_v, ea.iu, ea.ka, ea.kb, iz, ca);
+            column_load<ZPL>(P, sino_b, eb.iu, eb.ka, eb.kb, iz, cb);
+            column_sum<ZPL>(P, ca, ea.sf, ea.fa, ea.fb, ea.ka, ea.kb, iz, klo, va);
+            column_sum<ZPL>(P, cb, eb.sf, eb.fa, eb.fb, eb.ka, eb.kb, iz, klo, vb);
 #pragma unroll
-            for (int j = 0; j < KT; ++j) {
-                if (j >= n) break;
-                gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, ec[j].fa, ec[j].fb, ec[j].ka, ec[j].kb, iz, klo,
-                                   vacc);
+            for (int j = 1; j < KT; ++j) {
+                if (j >= na) break;
+                const CellEntry e = ent_a[j];
+                gather_column<ZPL>(P, sino_v, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, va);
             }
 #pragma unroll
-            for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
+            for (int j = 1; j < KT; ++j) {
+                if (j >= nb) break;
+                const CellEntry e = ent_b[j];
+                gather_column<ZPL>(P, sino_b, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, vb);
+            }
+#pragma unroll
+            for (int k = 0; k < ZPL; ++k) acc[k] += (double)va[k];
+            if (has_b) {
+#pragma unroll
+                for (int k = 0; k < ZPL; ++k) acc[k] += (double)vb[k];
+            }
         }
     } else {
         for (int64_t v = v0; v < v1; ++v) {
