@@ -38,12 +38,12 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "a7a366e5f68167c9b23fa0afa5b8c56da1d6c3a286bad958cca53bbdc11f96cb",
+    "source_sha256": "16d4036013d95ee109336eea61cd0baaf60a34100b7ca07ef851b8aa45b229c1",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
-    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.6e6,
-    "read_bytes": 987.6e6, "write_bytes": 264.9e6, "l2_hit_rate": 0.932,
+    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.4e6,
+    "read_bytes": 987.4e6, "write_bytes": 265.0e6, "l2_hit_rate": 0.933,
     # SQ_INSTS_VALU x 64 / nnz(A) of the same runs: VALU lane-instructions per intersection
-    "valu_lane_instr_per_intersection": 31.6,
+    "valu_lane_instr_per_intersection": 34.8,
     "profile": "profiles/gather_update_c2_128x16_counters.md",
 }
 
