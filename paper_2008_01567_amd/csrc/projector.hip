@@ -884,72 +884,109 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
         const int32_t *hdr = P.cell_hdr + v0 * ncell + cell;
         const CellEntry *ent = P.cell_ent + (v0 * ncell + cell) * KT;
         const float *sino_v = sino + v0 * view_len;
-        // Views go in pairs (a, b).  The first slot of a view is processed
-        // without a branch: when no column meets the cell it holds a zero
-        // piece (fa = fb = 0), whose lengths are exactly 0, and so does the
-        // missing b of an odd last pair (reading view a's sinogram).  Both
-        // first slots' rows are loaded before either view's sums are taken.
-        // Each view keeps its own FP32 sum, and they enter the FP64 sum in
-        // view order, as one view at a time would.
-        const CellEntry zero{0.0f, 0.0f, 0.0f, 0.0f, 0.0, 0, 0};
-        int na_next = 0, nb_next = 0;
-        CellEntry ea_next = zero, eb_next = zero;
-        if (v0 < v1) {
-            na_next = hdr[0];
-            ea_next = ent[0];
-        }
-        if (v0 + 1 < v1) {
-            nb_next = hdr[ncell];
-            eb_next = ent[ncell * KT];
-        }
-        for (int64_t v = v0; v < v1; v += 2, sino_v += 2 * view_len) {
-            const bool has_b = v + 1 < v1;
-            const int na = na_next, nb = nb_next;
-            const CellEntry ea = ea_next, eb = eb_next;
-            const CellEntry *ent_a = ent, *ent_b = ent + ncell * KT;
-            hdr += 2 * ncell;
-            ent += 2 * ncell * KT;
-            na_next = 0;
-            nb_next = 0;
-            ea_next = zero;
-            eb_next = zero;
-            if (v + 2 < v1) {
+        if constexpr (ZPL <= 2) {
+            // Views go in pairs (a, b).  The first slot of a view is processed
+            // without a branch: when no column meets the cell it holds a zero
+            // piece (fa = fb = 0), whose lengths are exactly 0, and so does the
+            // missing b of an odd last pair (reading view a's sinogram).  Both
+            // first slots' rows are loaded before either view's sums are taken.
+            // Each view keeps its own FP32 sum, and they enter the FP64 sum in
+            // view order, as one view at a time would.
+            const CellEntry zero{0.0f, 0.0f, 0.0f, 0.0f, 0.0, 0, 0};
+            int na_next = 0, nb_next = 0;
+            CellEntry ea_next = zero, eb_next = zero;
+            if (v0 < v1) {
                 na_next = hdr[0];
                 ea_next = ent[0];
             }
-            if (v + 3 < v1) {
+            if (v0 + 1 < v1) {
                 nb_next = hdr[ncell];
                 eb_next = ent[ncell * KT];
             }
-            const float *sino_b = has_b ? sino_v + view_len : sino_v;
-            float va[ZPL], vb[ZPL];
+            for (int64_t v = v0; v < v1; v += 2, sino_v += 2 * view_len) {
+                const bool has_b = v + 1 < v1;
+                const int na = na_next, nb = nb_next;
+                const CellEntry ea = ea_next, eb = eb_next;
+                const CellEntry *ent_a = ent, *ent_b = ent + ncell * KT;
+                hdr += 2 * ncell;
+                ent += 2 * ncell * KT;
+                na_next = 0;
+                nb_next = 0;
+                ea_next = zero;
+                eb_next = zero;
+                if (v + 2 < v1) {
+                    na_next = hdr[0];
+                    ea_next = ent[0];
+                }
+                if (v + 3 < v1) {
+                    nb_next = hdr[ncell];
+                    eb_next = ent[ncell * KT];
+                }
+                const float *sino_b = has_b ? sino_v + view_len : sino_v;
+                float va[ZPL], vb[ZPL];
 #pragma unroll
-            for (int k = 0; k < ZPL; ++k) {
-                va[k] = 0.0f;
-                vb[k] = 0.0f;
+                for (int k = 0; k < ZPL; ++k) {
+                    va[k] = 0.0f;
+                    vb[k] = 0.0f;
+                }
+                ColumnRows<ZPL> ca, cb;
+                column_load<ZPL>(P, sino_v, ea.iu, ea.ka, ea.kb, iz, ca);
+                column_load<ZPL>(P, sino_b, eb.iu, eb.ka, eb.kb, iz, cb);
+                column_sum<ZPL>(P, ca, ea.sf, ea.fa, ea.fb, ea.ka, ea.kb, iz, klo, va);
+                column_sum<ZPL>(P, cb, eb.sf, eb.fa, eb.fb, eb.ka, eb.kb, iz, klo, vb);
+#pragma unroll
+                for (int j = 1; j < KT; ++j) {
+                    if (j >= na) break;
+                    const CellEntry e = ent_a[j];
+                    gather_column<ZPL>(P, sino_v, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, va);
+                }
+#pragma unroll
+                for (int j = 1; j < KT; ++j) {
+                    if (j >= nb) break;
+                    const CellEntry e = ent_b[j];
+                    gather_column<ZPL>(P, sino_b, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, vb);
+                }
+#pragma unroll
+                for (int k = 0; k < ZPL; ++k) acc[k] += (double)va[k];
+                if (has_b) {
+#pragma unroll
+                    for (int k = 0; k < ZPL; ++k) acc[k] += (double)vb[k];
+                }
             }
-            ColumnRows<ZPL> ca, cb;
-            column_load<ZPL>(P, sino_v, ea.iu, ea.ka, ea.kb, iz, ca);
-            column_load<ZPL>(P, sino_b, eb.iu, eb.ka, eb.kb, iz, cb);
-            column_sum<ZPL>(P, ca, ea.sf, ea.fa, ea.fb, ea.ka, ea.kb, iz, klo, va);
-            column_sum<ZPL>(P, cb, eb.sf, eb.fa, eb.fb, eb.ka, eb.kb, iz, klo, vb);
+        } else {
+            // Deeper columns (ZPL > 2) take one view at a time: two views' rows
+            // in flight would cost more registers than the overlap gains.  The
+            // next view's entries are loaded while the current one is processed.
+            int n_next = 0;
+            CellEntry e_next[KT];
+            if (v0 < v1) {
+                n_next = *hdr;
 #pragma unroll
-            for (int j = 1; j < KT; ++j) {
-                if (j >= na) break;
-                const CellEntry e = ent_a[j];
-                gather_column<ZPL>(P, sino_v, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, va);
+                for (int j = 0; j < KT; ++j) e_next[j] = ent[j];
             }
+            for (int64_t v = v0; v < v1; ++v, sino_v += view_len) {
+                const int n = n_next;
+                CellEntry ec[KT];
 #pragma unroll
-            for (int j = 1; j < KT; ++j) {
-                if (j >= nb) break;
-                const CellEntry e = ent_b[j];
-                gather_column<ZPL>(P, sino_b, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, vb);
-            }
+                for (int j = 0; j < KT; ++j) ec[j] = e_next[j];
+                if (v + 1 < v1) {
+                    hdr += ncell;
+                    ent += ncell * KT;
+                    n_next = *hdr;
 #pragma unroll
-            for (int k = 0; k < ZPL; ++k) acc[k] += (double)va[k];
-            if (has_b) {
+                    for (int j = 0; j < KT; ++j) e_next[j] = ent[j];
+                }
+                float vacc[ZPL];
 #pragma unroll
-                for (int k = 0; k < ZPL; ++k) acc[k] += (double)vb[k];
+                for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
+#pragma unroll
+                for (int j = 0; j < KT; ++j) {
+                    if (j >= n) break;
+                    gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, ec[j].fa, ec[j].fb, ec[j].ka, ec[j].kb, iz, klo,
+                                       vacc);
+                }
+#pragma unroll
+                for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
             }
         }
     } else {
