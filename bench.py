@@ -38,7 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # library's plain copy kernel of known size in the same run (read x2.0, write
 # x1.0).  Valid only for the projector source they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "16d4036013d95ee109336eea61cd0baaf60a34100b7ca07ef851b8aa45b229c1",
+    "source_sha256": "47cf8e99ddf3b6692d3891c6ae5ff5b941d05a367604fbbdf3ae7a39c218c0c9",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
     "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.4e6,
     "read_bytes": 987.4e6, "write_bytes": 265.0e6, "l2_hit_rate": 0.933,
