@@ -680,14 +680,6 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
     p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
-__global__ void k_count_nonfinite(const float *__restrict__ a, int64_t n, int32_t *__restrict__ flag)
-{
-    int bad = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        bad += !isfinite(a[i]);
-    if (bad) atomicAdd(flag, bad);
-}
-
 unsigned grid_of(int64_t work, int per_block)
 {
     int64_t g = (work + per_block - 1) / per_block;
@@ -761,7 +753,7 @@ hipError_t launch_conv(int epi, const uint16_t *in, const uint16_t *w, const flo
                        uint16_t *out_bf, const uint16_t *mask, float *out_f, const float *v, int64_t v_stride,
                        int64_t v_off, float scale, hipStream_t s)
 {
-    ConvArgs A{in, w, bias, N, Z, Y, X, out_bf, mask, out_f, v, v_stride, v_off, scale};
+    ConvArgs A{in, w, bias, N, Z, Y, X, out_bf, mask, out_f, v, v_stride, v_off, scale, PackIn{}};
     const dim3 block(256);
     if (Z == 1) {
         // depth-1 images: only the depth-centre taps can be non-zero; row tiles staged in LDS
