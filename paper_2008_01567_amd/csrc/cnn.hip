@@ -77,11 +77,15 @@ NetShape make_shape(int cin0, int ptaps)
     return S;
 }
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+// FP32 -> BF16, round to nearest even (the hardware conversion of gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// two values, packed low | high << 16, in one conversion
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -135,8 +139,8 @@ __device__ __forceinline__ void conv_store(const ConvArgs &A, const v4f &acc, co
     const float o[4] = {acc[0] + b.x, acc[1] + b.y, acc[2] + b.z, acc[3] + b.w};
     if (EPI == EPI_RELU) {
         uint2 w;
-        w.x = (uint32_t)f2bf(fmaxf(o[0], 0.0f)) | ((uint32_t)f2bf(fmaxf(o[1], 0.0f)) << 16);
-        w.y = (uint32_t)f2bf(fmaxf(o[2], 0.0f)) | ((uint32_t)f2bf(fmaxf(o[3], 0.0f)) << 16);
+        w.x = f2bf2(fmaxf(o[0], 0.0f), fmaxf(o[1], 0.0f));
+        w.y = f2bf2(fmaxf(o[2], 0.0f), fmaxf(o[3], 0.0f));
         *reinterpret_cast<uint2 *>(A.out_bf + vox * CH + 4 * g) = w;
     } else if (EPI == EPI_MASK) {
         const uint2 m = *reinterpret_cast<const uint2 *>(A.mask + vox * CH + 4 * g);
@@ -241,9 +245,7 @@ __device__ __forceinline__ void tile_store_f32(uint4 *tile, const float (&reg)[T
         const int vi = threadIdx.x + 256 * k;
         if (vi >= TILE_VOX) continue;
         // f2bf(0) = 0, so the channels past the network's inputs stay zero
-        tile[2 * vi] = make_uint4((uint32_t)f2bf(reg[k][0]) | ((uint32_t)f2bf(reg[k][1]) << 16),
-                                  (uint32_t)f2bf(reg[k][2]) | ((uint32_t)f2bf(reg[k][3]) << 16),
-                                  (uint32_t)f2bf(reg[k][4]), 0u);
+        tile[2 * vi] = make_uint4(f2bf2(reg[k][0], reg[k][1]), f2bf2(reg[k][2], reg[k][3]), f2bf2(reg[k][4], 0.0f), 0u);
         tile[2 * vi + 1] = make_uint4(0u, 0u, 0u, 0u);
     }
 }
@@ -313,10 +315,14 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
 
 // First layer of the 2.5D denoiser on a plane sequence [T][S][H][W] (IN_SEQ):
 // a workgroup owns one (slice s, 8-row, 64-voxel) tile and walks along the
-// time points [t0, t1) of the chunk, keeping the tile of frames t - 2 .. t + 2
-// (one BF16 channel each, scaled as the input pack does) in a five-slot LDS
-// ring: each frame is staged once per tile instead of five times.  Frame
-// t + 3 is loaded into registers while time point t is multiplied.
+// time points [t0, t1) of the chunk.  Each thread keeps, for its staged
+// voxels of the tile (halo included), the BF16 values of the frames
+// clamp(t - 2) .. clamp(t + 2) (scaled as the input pack does) in registers,
+// two to a dword, so each frame is read from memory once per tile.  Per time
+// point it writes them as channels 0 .. 4 of the staged tile, in the layout
+// of the other layers (16 channels per voxel, 5 .. 15 zero), and the MFMAs
+// read one 8-byte operand per tap.  Frame t + 3 is loaded into registers while
+// time point t is multiplied.
 constexpr int RING_VOX = (TY + 2) * TROW;
 constexpr int RING_LD = (RING_VOX + 255) / 256;
 
@@ -338,9 +344,10 @@ __device__ __forceinline__ void frame_fetch(const ConvArgs &A, int f, int s, int
 __global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int t0, int t1)
 {
     __shared__ v4s wl[9 * CH * 4];
-    __shared__ uint16_t ring[5 * RING_VOX];
+    __shared__ uint4 tile[2 * RING_VOX];     // per staged voxel: channels 0 .. 7, then 8 .. 15 (zero)
     const v4s *wsrc = reinterpret_cast<const v4s *>(A.w) + 9 * CH * 4;     // the depth-centre taps
     for (int i = threadIdx.x; i < 9 * CH * 4; i += blockDim.x) wl[i] = wsrc[i];
+    for (int i = threadIdx.x; i < RING_VOX; i += blockDim.x) tile[2 * i + 1] = make_uint4(0u, 0u, 0u, 0u);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int T = A.pin.T, S = A.pin.S;
@@ -352,35 +359,40 @@ __global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int 
     const int si = (int)(b / nty);
     const float4 bias = conv_bias(A, g);
     const int xs = x0 + 16 * wave;
+    // the window of time point t0: channel c holds frame clamp(t0 - 2 + c)
+    float reg[RING_LD];
+    uint32_t w01[RING_LD], w23[RING_LD], w4[RING_LD];   // channels (0, 1), (2, 3), (4, 5 = 0)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        frame_fetch(A, min(max(t0 - 2 + c, 0), T - 1), si, y0, x0, reg);
+#pragma unroll
+        for (int k = 0; k < RING_LD; ++k) {
+            const uint32_t h = f2bf(reg[k]);
+            if (c == 0) w01[k] = h;
+            if (c == 1) w01[k] |= h << 16;
+            if (c == 2) w23[k] = h;
+            if (c == 3) w23[k] |= h << 16;
+            if (c == 4) w4[k] = h;
+        }
+    }
+    auto put = [&]() {
+#pragma unroll
+        for (int k = 0; k < RING_LD; ++k) {
+            const int vi = threadIdx.x + 256 * k;
+            if (vi < RING_VOX) tile[2 * vi] = make_uint4(w01[k], w23[k], w4[k], 0u);
+        }
+    };
+    put();
     __syncthreads();                         // the weights are staged
     v4s wr[9];                               // this lane's weight blocks, in registers
 #pragma unroll
     for (int q = 0; q < 9; ++q) wr[q] = wl[q * (CH * 4) + r * 4 + g];
-    float reg[RING_LD];
-    auto stage = [&](int f) {
-#pragma unroll
-        for (int k = 0; k < RING_LD; ++k) {
-            const int vi = threadIdx.x + 256 * k;
-            if (vi < RING_VOX) ring[(f % 5) * RING_VOX + vi] = f2bf(reg[k]);
-        }
-    };
-    // frames max(t0 - 2, 0) .. t0 + 2 (those that exist)
-    for (int f = max(t0 - 2, 0); f <= min(t0 + 2, T - 1); ++f) {
-        frame_fetch(A, f, si, y0, x0, reg);
-        stage(f);
-    }
+    const v4s *tl = reinterpret_cast<const v4s *>(tile);
     for (int t = t0; t < t1; ++t) {
-        __syncthreads();                     // frame t + 2 staged; frame t - 3's slot no longer read
+        __syncthreads();                     // the channels of time point t are staged
         const int fn = t + 3;
         if (fn < T) frame_fetch(A, fn, si, y0, x0, reg);
         if (xs < A.X) {
-            // channel c of this lane (c = 4g + j < 5) reads frame clamp(t + c - 2)
-            int sb[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = 4 * g + j;
-                sb[j] = c < 5 ? (min(max(t + c - 2, 0), T - 1) % 5) * RING_VOX : -1;
-            }
             const int64_t n = (int64_t)t * S + si - (int64_t)A.pin.n0;     // image within the chunk
             for (int ry = 0; ry < TY && y0 + ry < A.Y; ++ry) {
                 v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -388,18 +400,25 @@ __global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int 
                 for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
-                        const int o = (ry + dy) * TROW + 16 * wave + r + dx;
-                        v4s a;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) a[j] = sb[j] >= 0 ? (short)ring[sb[j] + o] : (short)0;
+                        // staged voxel (row ry + dy, column 16 wave + r + dx), channels 4g .. 4g + 3
+                        const v4s a = tl[((ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
                         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[dy * 3 + dx], a, acc, 0, 0, 0);
                     }
                 const int y = y0 + ry, xv = xs + r;
                 if (xv < A.X) conv_store<EPI_RELU>(A, acc, bias, (n * A.Y + y) * A.X + xv, 0, g);
             }
         }
-        __syncthreads();                     // every read of frame t - 2 (the slot of t + 3) is done
-        if (fn < T) stage(fn);
+        if (t + 1 < t1) {
+            __syncthreads();                 // every read of time point t's channels is done
+            // one time point on: channels shift down by one, frame clamp(t + 3) enters as channel 4
+#pragma unroll
+            for (int k = 0; k < RING_LD; ++k) {
+                w01[k] = (w01[k] >> 16) | (w23[k] << 16);
+                w23[k] = (w23[k] >> 16) | (w4[k] << 16);
+                if (fn < T) w4[k] = f2bf(reg[k]);
+            }
+            put();
+        }
     }
 }
 
@@ -791,7 +810,7 @@ hipError_t cnn_forward(msf_cnn *C, const PackIn &in, int N, int Z, int Y, int X,
         ConvArgs A{nullptr, C->wf, C->bias, N, Z, Y, X, C->h[1], nullptr, nullptr, nullptr, 0, 0, 0.0f, in};
         const int64_t tiles_per_image = (int64_t)((Y + TY - 1) / TY) * ((X + TXW - 1) / TXW);
         if (in.mode == IN_SEQ && in.n0 % in.S == 0 && N % in.S == 0 && (int64_t)in.S * tiles_per_image <= 0x7fffffff) {
-            // whole time points: walk along t with the five-frame ring
+            // whole time points: walk along t with each voxel's five-frame window in registers
             const int t0 = (int)(in.n0 / in.S), t1 = t0 + N / in.S;
             hipLaunchKernelGGL(k_conv2d_first_seq, dim3((unsigned)(in.S * tiles_per_image)), dim3(256), 0, s, A, t0,
                                t1);
