@@ -295,6 +295,17 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
         }
         const int xs = pc.x0 + 16 * wave;    // this wave's segment
         if (xs >= A.X) continue;             // wave-uniform; no barrier until the next tile
+        // the residual output adds the tile's base values, loaded before the MFMAs (lanes g = 0 store)
+        float vb[EPI == EPI_RESID ? TY : 1];
+        if constexpr (EPI == EPI_RESID) {
+#pragma unroll
+            for (int ry = 0; ry < TY; ++ry) {
+                const int y = pc.y0 + ry, xv = xs + r;
+                vb[ry] = (g == 0 && y < A.Y && xv < A.X)
+                             ? A.v[(int64_t)pc.n * A.v_stride + A.v_off + (int64_t)y * A.X + xv]
+                             : 0.0f;
+            }
+        }
         for (int ry = 0; ry < TY && pc.y0 + ry < A.Y; ++ry) {
             v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -306,9 +317,12 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
                     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[dy * 3 + dx], a, acc, 0, 0, 0);
                 }
             const int y = pc.y0 + ry, xv = xs + r;
-            if (xv < A.X)
-                conv_store<EPI>(A, acc, bias, ((int64_t)pc.n * A.Y + y) * A.X + xv,
-                                (int64_t)pc.n * A.v_stride + A.v_off + (int64_t)y * A.X + xv, g);
+            const int64_t vox = ((int64_t)pc.n * A.Y + y) * A.X + xv;
+            if constexpr (EPI == EPI_RESID) {
+                if (xv < A.X && g == 0) A.out_f[vox] = vb[ry] + A.scale * (acc[0] + bias.x);
+            } else {
+                if (xv < A.X) conv_store<EPI>(A, acc, bias, vox, 0, g);
+            }
         }
     }
 }
