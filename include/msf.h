@@ -145,8 +145,9 @@ msf_status msf_plan_get_tiles(const msf_plan *plan, msf_tiles *tiles);
  * events on the given stream, plan-owned buffers; the better of two runs
  * after a warm-up run) for every supported launch shape on this plan's
  * geometry, with the on-the-fly and the table-driven adjoint (the latter
- * with the forward's walk table), then the ray-driven adjoint at the best
- * shape, and applies the fastest (forward + adjoint) pair.
+ * with the forward's walk table), times the three fastest again (the best
+ * of five runs), then the ray-driven adjoint at the best shape, and applies
+ * the fastest (forward + adjoint) pair.
  * cache_path (may be NULL): text file of "key tiles" lines, key = GPU arch +
  * geometry sizes + a hash of the angle list; a hit is applied without timing,
  * a miss is appended.  chosen (host, may be NULL) receives the shape. */
