@@ -94,6 +94,24 @@ def test_batched_equals_per_frame(msf):
         assert rel_l2(x1.cpu().numpy()[0], xb[f]) <= 1e-5
 
 
+def test_frame_shards_equal_batch(msf):
+    """The frames split into two shards (as across two GPUs: separate plans, no
+    exchange) give the batched result on every frame."""
+    name = "c3s"
+    cfg, g, x0, v, y, lam = problem(name)
+    xb, _ = msf.Plan(g).prox_solve(_dev(v), _dev(y), _dev(lam), cfg.sigma, tol=0.0, max_iter=300)
+    xb = xb.cpu().numpy()
+    half = g.n_frames // 2
+    for frames in (list(range(half)), list(range(half, g.n_frames))):
+        gs = g.subset(frames)
+        ys = np.concatenate([y[g.sino_slice(f)] for f in frames])
+        ls = np.concatenate([lam[g.sino_slice(f)] for f in frames])
+        xs, _ = msf.Plan(gs).prox_solve(_dev(v[frames]), _dev(ys), _dev(ls), cfg.sigma, tol=0.0, max_iter=300)
+        xs = xs.cpu().numpy()
+        for i, f in enumerate(frames):
+            assert rel_l2(xs[i], xb[f]) <= 1e-5, (frames, f)
+
+
 def test_special_cases(msf):
     cfg, g, x0, v, y, lam = problem("c1")
     plan = msf.Plan(g)
