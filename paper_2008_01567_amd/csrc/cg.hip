@@ -197,23 +197,34 @@ __global__ __launch_bounds__(VB) void k_scale_feature(VolArgs A)
     }
 }
 
-// per frame: learned start kept (IS_CNN = 1): r = p; else x = v, p = r
+// per frame: learned start kept (IS_CNN = 1): r = p; else x = v, p = r.
+// Either way the ||p||^2 partials of the direction that is kept are
+// rewritten, in the order k_vol_residual sums them, so the first step's
+// <p, H p> uses that direction (a rejected frame continues bit for bit as
+// the solve from v would).
 __global__ __launch_bounds__(VB) void k_vol_select(VolArgs A, const int32_t *use_cnn)
 {
     const int f = blockIdx.y;
     const bool keep = use_cnn[f] != 0;
     const int64_t base = (int64_t)f * A.nvox;
+    double s = 0.0;
     for (int k = 0; k < VE; ++k) {
         const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
         if (i < A.nvox) {
+            float pf;
             if (keep) {
-                A.r[base + i] = A.p[base + i];
+                pf = A.p[base + i];
+                A.r[base + i] = pf;
             } else {
+                pf = A.r[base + i];
                 A.x[base + i] = A.vin[base + i];
-                A.p[base + i] = A.r[base + i];
+                A.p[base + i] = pf;
             }
+            s += (double)pf * (double)pf;
         }
     }
+    s = block_sum(s);
+    if (threadIdx.x == 0) A.part[(int64_t)f * A.bpf + blockIdx.x] = s;
 }
 
 // x += alpha p;  r -= alpha (bp + p / sigma^2);  bp = 0;  partial ||r||^2.
