@@ -1,7 +1,8 @@
 """Parity at the benchmark's full size (128^3 x 16 frames, 192^2 detector,
-16 views per frame), in the launch configuration bench.py times: the whole
-batch runs on the GPU; the FP64 oracle checks sampled frames completely and
-sampled rays / voxels of the others."""
+16 views per frame), in the launch configuration bench.py times (the plan is
+autotuned, as the benchmark's is): the whole batch runs on the GPU; the FP64
+oracle checks sampled frames completely and sampled rays / voxels of the
+others."""
 import numpy as np
 import pytest
 
@@ -30,6 +31,7 @@ def setup():
     y = y.astype(np.float32).astype(np.float64)
     lam = lam.astype(np.float32).astype(np.float64)
     plan = msf.Plan(g)
+    print("autotuned launch shape", plan.autotune(), flush=True)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     return msf, cfg, g, x0, v, y, lam, mats, plan, dev
 
