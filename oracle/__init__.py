@@ -79,12 +79,18 @@ def lib():
         L.or_project_rays.argtypes = [gp, dp, ip, ip, ip, C.c_int32, dp, dp]
         L.or_voxel_columns.argtypes = [gp, dp, C.c_int32, lp, C.c_int32, ip, lp, dp, C.c_int32]
         L.or_num_threads.restype = C.c_int32
+        L.or_set_num_threads.argtypes = [C.c_int32]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's following calls (for timing it)."""
+    lib().or_set_num_threads(int(n))
 
 
 def cgeom(geom) -> _Geom:

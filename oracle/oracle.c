@@ -434,3 +434,14 @@ int32_t or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the following parallel regions (timing of the oracle itself). */
+void or_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
