@@ -65,7 +65,7 @@ def test_forward_matches_oracle(msf, shape):
     want = want[:, 0]
     err = rel_l2(got - v, want - v)
     print(shape, "forward residual rel err %.2e" % err, flush=True)
-    assert err <= 3e-3
+    assert err <= 1e-3        # observed 2.2e-6 (small), 9.8e-5 (tiled)
     assert np.abs(got - want).max() <= 1e-3 * np.abs(want - v).max() * 10
 
 
@@ -87,7 +87,7 @@ def test_gradients_match_oracle(msf, shape):
         n = co * ci * 27 + co
         err = rel_l2(grad[o:o + n], ograd[o:o + n])
         print(shape, "layer", li, "grad rel err %.2e" % err, flush=True)
-        assert err <= 1e-2
+        assert err <= 1e-3    # observed 1.8e-6 ... 1.3e-4 over both shapes and all layers
         o += n
     assert np.array_equal(net.params(), ocnn.flatten(params).astype(np.float32))   # apply=0 leaves weights
 
