@@ -326,6 +326,25 @@ msf_status msf_plan_get_timing(const msf_plan *plan, msf_timing *out);
 msf_status msf_fixture_correct(msf_plan *plan, const float *x, const float *y, double mask_radius, double blur_std,
                                float *y_corr, double *c_out, void *stream);
 
+/* Scratch limit of msf_fixture_correct_noalloc, in bytes (64 MiB). */
+#define MSF_FIXTURE_SCRATCH_BYTES (64u << 20)
+
+/* msf_fixture_correct for callers that cannot allocate device memory during
+ * the call (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, same results bit for bit, no
+ * hipMalloc / hipFree or other allocating routine.  Its scratch (the blurred
+ * sinogram, per-view inner products and per-frame fits:
+ * 16 n_views + 8 n_frames + 4 n_meas bytes, each part rounded up to 256) is
+ * a fixed device array of MSF_FIXTURE_SCRATCH_BYTES that each GPU holds
+ * until the process ends; a geometry that needs more returns MSF_EINVAL
+ * before any device work (128^3 x 16 with 192^2 x 256 views fits, 38 MB).
+ * The plan (created beforehand) still provides the projector tables and its
+ * internal buffers.  Call with the plan's device current.  Every call on one
+ * GPU shares that GPU's scratch: calls that overlap in time on one GPU (from
+ * any plan, stream or thread) race and give wrong results. */
+msf_status msf_fixture_correct_noalloc(msf_plan *plan, const float *x, const float *y, double mask_radius,
+                                       double blur_std, float *y_corr, double *c_out, void *stream);
+
 /* Number of ray-voxel pieces of positive length (the nonzeros of A_n) per
  * frame, counted by the forward projector's own traversal.  per_frame: host
  * [n_frames].  Synchronises the stream. */

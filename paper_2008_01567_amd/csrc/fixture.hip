@@ -13,6 +13,8 @@
 #include "msf_internal.h"
 
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 namespace {
@@ -129,14 +131,100 @@ unsigned grid_of(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
 }
 
-#define FCHK(expr)                                           \
+// Scratch of the allocation-free entry point: the blurred sinogram p, the
+// per-view inner products and the per-frame fits, in one file-scope device
+// array.  Each GPU the library runs on holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): it asks each device for the array's
+// address once and passes that.
+constexpr size_t SCRATCH_BYTES = (size_t)MSF_FIXTURE_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[SCRATCH_BYTES / sizeof(double)];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of `scratch` on the current device (looked up on the first call per device).
+msf_status scratch_on_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("device index beyond the scratch table");
+        return MSF_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MSF_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Blur taps of std blur_std over 2 ceil(3 std) + 1 pixels, normalised.
+msf_status make_taps(double blur_std, Taps &T)
+{
+    const int r = (int)std::ceil(3.0 * blur_std);
+    if (!(blur_std > 0.0) || !std::isfinite(blur_std) || r > MAX_R) {
+        set_error("blur_std must be > 0 with 3 std <= 64 pixels");
+        return MSF_EINVAL;
+    }
+    T = Taps{};
+    T.r = r;
+    double sum = 0.0;
+    for (int t = -r; t <= r; ++t) sum += std::exp(-0.5 * t * t / (blur_std * blur_std));
+    for (int t = -r; t <= r; ++t) T.w[t + r] = std::exp(-0.5 * t * t / (blur_std * blur_std)) / sum;
+    return MSF_OK;
+}
+
+#define RCHK(expr)                                           \
     do {                                                     \
         hipError_t e_ = (expr);                              \
-        if (e_ != hipSuccess) {                              \
-            release();                                       \
-            return hip_fail(e_, #expr);                      \
-        }                                                    \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
     } while (0)
+
+// The correction on the stream, with its scratch given: ptmp [n_meas] FP32,
+// dots [2 n_views] FP64, cdev [n_frames] FP64 (every element is written
+// before it is read).  Leaves c in cdev; nothing is synchronised.
+msf_status run_correction(msf_plan *P, const float *x, const float *y, double mask_radius, const Taps &T,
+                          float *y_corr, float *ptmp, double *dots, double *cdev, hipStream_t s)
+{
+    const int64_t nm = P->nmeas_total, per_view = (int64_t)P->nu * P->nv;
+    // x_m (internal layout) and A x_m
+    RCHK(vol_to_internal(*P, x, P->p, 0, nullptr, s));
+    hipLaunchKernelGGL(k_cyl_mask, dim3(grid_of(P->nvox_total)), dim3(256), 0, s, P->p, P->nvox_total, P->nx, P->ny,
+                       P->nz, mask_radius * mask_radius);
+    RCHK(hipGetLastError());
+    RCHK(launch_fill(P->sz, nm, 0.0f, s));
+    RCHK(launch_forward(*P, PM_PLAIN, P->p, nullptr, P->sz, false, s));
+    // e = y - A x_m  (in sz; y stays in sy)
+    RCHK(sino_to_internal(*P, y, P->sy, 0, nullptr, s));
+    hipLaunchKernelGGL(k_rsub, dim3(grid_of(nm)), dim3(256), 0, s, P->sz, P->sy, nm);
+    RCHK(hipGetLastError());
+    // p = blur(e): along v into slam, then along u into ptmp
+    if (nm > 0) {
+        hipLaunchKernelGGL(k_blur, dim3(grid_of(nm)), dim3(256), 0, s, P->sz, P->slam, nm, P->nu, P->nv, 0, T);
+        hipLaunchKernelGGL(k_blur, dim3(grid_of(nm)), dim3(256), 0, s, P->slam, ptmp, nm, P->nu, P->nv, 1, T);
+        RCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_view_dots, dim3((unsigned)P->n_views), dim3(256), 0, s, P->sz, ptmp, per_view, dots);
+        RCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_frame_fit, dim3((P->nf + 63) / 64), dim3(64), 0, s, dots, P->d_view_offset, P->nf, cdev);
+    RCHK(hipGetLastError());
+    if (nm > 0) {
+        hipLaunchKernelGGL(k_apply, dim3(grid_of(nm)), dim3(256), 0, s, P->sy, ptmp, cdev, P->d_view_offset, P->nf,
+                           per_view, nm, P->sz);
+        RCHK(hipGetLastError());
+    }
+    RCHK(sino_to_public(*P, P->sz, y_corr, s));
+    return MSF_OK;
+}
 
 }  // namespace
 
@@ -146,19 +234,11 @@ extern "C" msf_status msf_fixture_correct(msf_plan *P, const float *x, const flo
     set_error("");
     if (!P || !x || !y || !y_corr) { set_error("null argument"); return MSF_EINVAL; }
     if (!(mask_radius > 0.0 && std::isfinite(mask_radius))) { set_error("mask_radius must be > 0"); return MSF_EINVAL; }
-    const int r = (int)std::ceil(3.0 * blur_std);
-    if (!(blur_std > 0.0) || !std::isfinite(blur_std) || r > MAX_R) {
-        set_error("blur_std must be > 0 with 3 std <= 64 pixels");
-        return MSF_EINVAL;
-    }
+    Taps T;
+    msf_status st = make_taps(blur_std, T);
+    if (st != MSF_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    Taps T{};
-    T.r = r;
-    double sum = 0.0;
-    for (int t = -r; t <= r; ++t) sum += std::exp(-0.5 * t * t / (blur_std * blur_std));
-    for (int t = -r; t <= r; ++t) T.w[t + r] = std::exp(-0.5 * t * t / (blur_std * blur_std)) / sum;
-
-    const int64_t nm = P->nmeas_total, per_view = (int64_t)P->nu * P->nv;
+    const int64_t nm = P->nmeas_total;
     float *ptmp = nullptr;
     double *dots = nullptr, *cdev = nullptr;
     auto release = [&]() {
@@ -166,41 +246,56 @@ extern "C" msf_status msf_fixture_correct(msf_plan *P, const float *x, const flo
         if (dots) (void)hipFree(dots);
         if (cdev) (void)hipFree(cdev);
     };
-    FCHK(hipMalloc((void **)&ptmp, sizeof(float) * std::max<int64_t>(nm, 1)));
-    FCHK(hipMalloc((void **)&dots, sizeof(double) * 2 * std::max<int64_t>(P->n_views, 1)));
-    FCHK(hipMalloc((void **)&cdev, sizeof(double) * P->nf));
-
-    // x_m (internal layout) and A x_m
-    FCHK(vol_to_internal(*P, x, P->p, 0, nullptr, s));
-    hipLaunchKernelGGL(k_cyl_mask, dim3(grid_of(P->nvox_total)), dim3(256), 0, s, P->p, P->nvox_total, P->nx, P->ny,
-                       P->nz, mask_radius * mask_radius);
-    FCHK(hipGetLastError());
-    FCHK(launch_fill(P->sz, nm, 0.0f, s));
-    FCHK(launch_forward(*P, PM_PLAIN, P->p, nullptr, P->sz, false, s));
-    // e = y - A x_m  (in sz; y stays in sy)
-    FCHK(sino_to_internal(*P, y, P->sy, 0, nullptr, s));
-    hipLaunchKernelGGL(k_rsub, dim3(grid_of(nm)), dim3(256), 0, s, P->sz, P->sy, nm);
-    FCHK(hipGetLastError());
-    // p = blur(e): along v into slam, then along u into ptmp
-    if (nm > 0) {
-        hipLaunchKernelGGL(k_blur, dim3(grid_of(nm)), dim3(256), 0, s, P->sz, P->slam, nm, P->nu, P->nv, 0, T);
-        hipLaunchKernelGGL(k_blur, dim3(grid_of(nm)), dim3(256), 0, s, P->slam, ptmp, nm, P->nu, P->nv, 1, T);
-        FCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_view_dots, dim3((unsigned)P->n_views), dim3(256), 0, s, P->sz, ptmp, per_view, dots);
-        FCHK(hipGetLastError());
+    hipError_t e = hipMalloc((void **)&ptmp, sizeof(float) * std::max<int64_t>(nm, 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&dots, sizeof(double) * 2 * std::max<int64_t>(P->n_views, 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&cdev, sizeof(double) * P->nf);
+    if (e != hipSuccess) {
+        release();
+        return hip_fail(e, "hipMalloc fixture buffers");
     }
-    hipLaunchKernelGGL(k_frame_fit, dim3((P->nf + 63) / 64), dim3(64), 0, s, dots, P->d_view_offset, P->nf, cdev);
-    FCHK(hipGetLastError());
-    if (nm > 0) {
-        hipLaunchKernelGGL(k_apply, dim3(grid_of(nm)), dim3(256), 0, s, P->sy, ptmp, cdev, P->d_view_offset, P->nf,
-                           per_view, nm, P->sz);
-        FCHK(hipGetLastError());
-    }
-    FCHK(sino_to_public(*P, P->sz, y_corr, s));
+    st = run_correction(P, x, y, mask_radius, T, y_corr, ptmp, dots, cdev, s);
     std::vector<double> hc(P->nf, 0.0);
-    FCHK(hipMemcpyAsync(hc.data(), cdev, sizeof(double) * P->nf, hipMemcpyDeviceToHost, s));
-    FCHK(hipStreamSynchronize(s));
+    if (st == MSF_OK) {
+        e = hipMemcpyAsync(hc.data(), cdev, sizeof(double) * P->nf, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "fixture result");
+    }
     release();
+    if (st == MSF_OK && c_out)
+        for (int f = 0; f < P->nf; ++f) c_out[f] = hc[f];
+    return st;
+}
+
+extern "C" msf_status msf_fixture_correct_noalloc(msf_plan *P, const float *x, const float *y, double mask_radius,
+                                                  double blur_std, float *y_corr, double *c_out, void *stream)
+{
+    set_error("");
+    if (!P || !x || !y || !y_corr) { set_error("null argument"); return MSF_EINVAL; }
+    if (!(mask_radius > 0.0 && std::isfinite(mask_radius))) { set_error("mask_radius must be > 0"); return MSF_EINVAL; }
+    Taps T;
+    msf_status st = make_taps(blur_std, T);
+    if (st != MSF_OK) return st;
+    // scratch layout: dots [2 n_views] FP64 | cdev [n_frames] FP64 | ptmp [n_meas] FP32, each 256-byte aligned
+    const size_t off_c = align256(sizeof(double) * 2 * (size_t)P->n_views);
+    const size_t off_p = off_c + align256(sizeof(double) * (size_t)P->nf);
+    const size_t need = off_p + sizeof(float) * (size_t)P->nmeas_total;
+    if (need > SCRATCH_BYTES) {
+        set_error("msf_fixture_correct_noalloc: this geometry needs " + std::to_string(need) +
+                  " bytes of scratch, more than its " + std::to_string(SCRATCH_BYTES) +
+                  "-byte limit (use msf_fixture_correct)");
+        return MSF_EINVAL;
+    }
+    void *base = nullptr;
+    if ((st = scratch_on_current_device(&base)) != MSF_OK) return st;
+    char *b = (char *)base;
+    double *dots = (double *)b, *cdev = (double *)(b + off_c);
+    float *ptmp = (float *)(b + off_p);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = run_correction(P, x, y, mask_radius, T, y_corr, ptmp, dots, cdev, s)) != MSF_OK) return st;
+    // c through the plan's pinned staging buffer (sized for more than n_frames doubles at creation)
+    double *hc = (double *)P->host_stage;
+    RCHK(hipMemcpyAsync(hc, cdev, sizeof(double) * P->nf, hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
     if (c_out)
         for (int f = 0; f < P->nf; ++f) c_out[f] = hc[f];
     return MSF_OK;

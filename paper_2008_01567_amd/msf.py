@@ -84,7 +84,7 @@ EXPORTS = ["msf_solve_opts_default", "msf_plan_create", "msf_plan_destroy", "msf
            "msf_last_error", "msf_version", "msf_plan_set_timing", "msf_plan_get_timing",
            "msf_count_intersections", "msf_prox_features", "msf_cnn_create", "msf_cnn_destroy",
            "msf_cnn_get_params", "msf_cnn_infer", "msf_cnn_train_step", "msf_mace_opts_default", "msf_mace_run", "msf_plan_autotune",
-           "msf_fixture_correct", "msf_cnn_create_denoiser", "msf_cnn_kind", "msf_cnn_n_params", "msf_denoise25"]
+           "msf_fixture_correct", "msf_fixture_correct_noalloc", "msf_cnn_create_denoiser", "msf_cnn_kind", "msf_cnn_n_params", "msf_denoise25"]
 
 
 def lib():
@@ -111,6 +111,7 @@ def lib():
         L.msf_plan_get_timing.argtypes = [vp, C.POINTER(msf_timing)]
         L.msf_count_intersections.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.msf_fixture_correct.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, C.POINTER(C.c_double), vp]
+        L.msf_fixture_correct_noalloc.argtypes = L.msf_fixture_correct.argtypes
         L.msf_prox_features.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
         L.msf_mace_opts_default.argtypes = [C.POINTER(msf_mace_opts)]
         L.msf_plan_autotune.argtypes = [vp, C.c_char_p, C.POINTER(msf_tiles), vp]
@@ -229,6 +230,15 @@ class Plan:
         _check(lib().msf_fixture_correct(self._h, _ptr(x, self.n_vox), _ptr(y, self.n_meas), float(mask_radius),
                                          float(blur_std), _ptr(out, self.n_meas),
                                          c.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+        return out, c
+
+    def fixture_correct_noalloc(self, x, y, mask_radius, blur_std, out, stream=None):
+        """msf_fixture_correct_noalloc: the same correction with the library's fixed
+        scratch and no device allocation (out must be given); returns (out, c)."""
+        c = np.zeros(self.geom.n_frames)
+        _check(lib().msf_fixture_correct_noalloc(self._h, _ptr(x, self.n_vox), _ptr(y, self.n_meas),
+                                                 float(mask_radius), float(blur_std), _ptr(out, self.n_meas),
+                                                 c.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
         return out, c
 
     def count_intersections(self, stream=None) -> np.ndarray:

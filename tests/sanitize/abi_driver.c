@@ -83,6 +83,8 @@ int main(void)
     expect(msf_plan_autotune(NULL, NULL, NULL, NULL) == MSF_EINVAL, "autotune");
     expect(msf_count_intersections(NULL, NULL, NULL) == MSF_EINVAL, "count_intersections");
     expect(msf_fixture_correct(NULL, NULL, NULL, 10.0, 1.0, NULL, NULL, NULL) == MSF_EINVAL, "fixture_correct");
+    expect(msf_fixture_correct_noalloc(NULL, NULL, NULL, 10.0, 1.0, NULL, NULL, NULL) == MSF_EINVAL,
+           "fixture_correct_noalloc");
     expect(msf_mace_run(NULL, NULL, NULL, NULL, 0.5, &mo, NULL, NULL, NULL) == MSF_EINVAL, "mace_run");
     expect(msf_cnn_get_params(NULL, NULL) == MSF_EINVAL, "cnn_get_params");
     expect(msf_cnn_infer(NULL, NULL, NULL, 1, 1, 8, 8, NULL, NULL) == MSF_EINVAL, "cnn_infer");

@@ -102,6 +102,8 @@ def test_entry_points_reject_null_handles():
         "msf_plan_autotune": lambda: L.msf_plan_autotune(None, None, None, None),
         "msf_count_intersections": lambda: L.msf_count_intersections(None, None, None),
         "msf_fixture_correct": lambda: L.msf_fixture_correct(None, None, None, 10.0, 1.0, None, None, None),
+        "msf_fixture_correct_noalloc": lambda: L.msf_fixture_correct_noalloc(None, None, None, 10.0, 1.0, None, None,
+                                                                             None),
         "msf_mace_run": lambda: L.msf_mace_run(None, None, None, None, 0.5, C.byref(mo), None, None, None),
         "msf_cnn_get_params": lambda: L.msf_cnn_get_params(None, None),
         "msf_cnn_infer": lambda: L.msf_cnn_infer(None, None, None, 1, 1, 8, 8, None, None),
