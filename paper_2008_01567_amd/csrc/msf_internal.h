@@ -28,10 +28,11 @@ enum ProjMode : int {
 
 // Everything a projector launch needs (passed by value as a kernel argument).
 // One detector column's piece of the xy line inside one xy cell (the voxel-
-// driven adjoint's table): s range [fa, fb], slopes ka, kb bounding the rows
-// through a voxel, the column's source offset sf and its index iu.
+// driven adjoint's table): s range [fa, fb], the smaller and larger of the
+// detector rows per unit z at the piece's two ends (rmin, rmax: they bound the
+// rows through a voxel), the column's source offset sf and its index iu.
 struct CellEntry {
-    float fa, fb, ka, kb;
+    float fa, fb, rmin, rmax;
     double sf;
     int32_t iu, pad;
 };

@@ -665,20 +665,24 @@ struct GatherUpdate {
 
 // Length of the ray with crossing slope im (see zplane_s) inside z slab
 // [klo, klo + 1] and xy piece [fa, fb] of a column whose source sits at
-// s = -sf; <= 0 when disjoint.  For zp = 0 the table holds a huge finite
-// slope, so the slab holding z = 0 gets the whole piece and every other slab
-// nothing, as in the forward walk.
+// s = -sf, up to its sign: the slab's two plane crossings e1, e2 clamped to
+// the piece, subtracted.  Its magnitude is the length (0 when disjoint).  For
+// zp = 0 the table holds a huge finite slope, so the slab holding z = 0 gets
+// the whole piece and every other slab nothing, as in the forward walk.
 //
 // With e_lo = min(e1, e2) and e_hi = max(e1, e2) the length is
-// min(fb, e_hi) - max(fa, e_lo).  The medians med3(e1, e2, fb) and
-// med3(e1, e2, fa) equal those two terms whenever the difference is
-// positive (then fb > e_lo and fa < e_hi), and otherwise still give a
-// difference <= 0, so the clamped length is the same bit for bit with two
-// instructions instead of six.
-__device__ __forceinline__ float slab_piece(double im, double sf, double klo, float fa, float fb)
+// max(min(fb, e_hi) - max(fa, e_lo), 0).  Clamping is monotone, so
+// |clamp(e2, fa, fb) - clamp(e1, fa, fb)| = clamp(e_hi) - clamp(e_lo), and
+// when the slab meets the piece clamp(e_hi) = min(fb, e_hi) and clamp(e_lo) =
+// max(fa, e_lo): the same two FP32 values the forward projector subtracts, so
+// the length is the same bit for bit; when they are disjoint both clamps are
+// the same end of the piece and the difference is exactly 0.  The sign is
+// dropped for free by the absolute-value source modifier of the multiply-add
+// that uses the length.
+__device__ __forceinline__ float slab_piece_signed(double im, double sf, double klo, float fa, float fb)
 {
     const float e1 = (float)fma(klo, im, -sf), e2 = (float)fma(klo + 1.0, im, -sf);
-    return __builtin_amdgcn_fmed3f(e1, e2, fb) - __builtin_amdgcn_fmed3f(e1, e2, fa);
+    return __builtin_amdgcn_fmed3f(e2, fa, fb) - __builtin_amdgcn_fmed3f(e1, fa, fb);
 }
 
 // Detector columns [iu0, iu1] whose xy line can meet cell (ix, iy) in view v:
@@ -707,10 +711,13 @@ __device__ __forceinline__ void cell_columns(const ProjParams &P, int64_t v, int
 
 // Piece [fa, fb] of column E's xy line inside cell (ix, iy), with the forward
 // walk's crossing expressions (so the lengths match A's bit for bit), and the
-// slopes ka, kb (zp per unit z at the piece's ends) that bound the detector
-// rows through a voxel of the cell.  False when the line misses the cell.
-__device__ __forceinline__ bool cell_piece(const ColEntry &E, int ix, int iy, float &fa, float &fb, float &ka,
-                                           float &kb)
+// detector rows per unit of z at the piece's two ends (the ray of height zp
+// on the detector is at z = zp (s + sf) / lxy), smaller one in rmin, larger
+// in rmax: rows through a voxel [z, z + 1] lie between z * rmin and
+// (z + 1) * rmax for z >= 0, between z * rmax and (z + 1) * rmin below.
+// False when the line misses the cell.
+__device__ __forceinline__ bool cell_piece(const ColEntry &E, int ix, int iy, float inv_dv, float &fa, float &fb,
+                                           float &rmin, float &rmax)
 {
     if (!E.hit) return false;
     // a line parallel to an axis stays in one cell row
@@ -724,10 +731,11 @@ __device__ __forceinline__ bool cell_piece(const ColEntry &E, int ix, int iy, fl
     fa = (float)sa;
     fb = (float)sb;
     if (!(fb > fa)) return false;
-    // ray height z = zp (s + sf) / lxy
     const float lxyf = (float)E.lxy;
-    ka = lxyf * __builtin_amdgcn_rcpf((float)(sa + E.sf));
-    kb = lxyf * __builtin_amdgcn_rcpf((float)(sb + E.sf));
+    const float ka = lxyf * __builtin_amdgcn_rcpf((float)(sa + E.sf));
+    const float kb = lxyf * __builtin_amdgcn_rcpf((float)(sb + E.sf));
+    rmin = fminf(ka, kb) * inv_dv;
+    rmax = fmaxf(ka, kb) * inv_dv;
     return true;
 }
 
@@ -746,11 +754,12 @@ __global__ void k_cell_table(const ProjParams P, int64_t n_views, int32_t *__res
     const int ix = cell % P.nx, iy = cell / P.nx;
     int iu0, iu1;
     cell_columns(P, v, ix, iy, iu0, iu1);
+    const float inv_dv = (float)(1.0 / P.dv);
     int n = 0;
     for (int iu = iu0; iu <= iu1; ++iu) {
         const ColEntry &E = P.cols[v * P.nu + iu];
         CellEntry c;
-        if (!cell_piece(E, ix, iy, c.fa, c.fb, c.ka, c.kb)) continue;
+        if (!cell_piece(E, ix, iy, inv_dv, c.fa, c.fb, c.rmin, c.rmax)) continue;
         c.sf = E.sf;
         c.iu = iu;
         c.pad = 0;
@@ -762,12 +771,13 @@ __global__ void k_cell_table(const ProjParams P, int64_t n_views, int32_t *__res
     if (n > K) atomicAdd(overflow, 1);
 }
 
-// The voxels of one lane (z = iz[k]) against column iu's piece [fa, fb]:
-// add length * pre-scaled sinogram value of every detector row whose ray
-// passes through the voxel inside the piece.  In two phases, so that a caller
-// can issue the loads of several columns before their arithmetic:
-// column_load finds every voxel's first candidate row and loads the first
-// two candidates, column_sum takes the lengths (and reads any further rows).
+// The voxels of one lane (lower z face zlo[k], as a float and an exact double
+// klo[k]) against column iu's piece [fa, fb]: add length * pre-scaled
+// sinogram value of every detector row whose ray passes through the voxel
+// inside the piece.  In two phases, so that a caller can issue the loads of
+// several columns before their arithmetic: column_load finds every voxel's
+// first candidate row and loads the first two candidates, column_sum takes
+// the lengths (and reads any further rows).
 template <int ZPL>
 struct ColumnRows {
     __amdgpu_buffer_rsrc_t srow, irow;   // the column's sinogram values and crossing slopes
@@ -776,29 +786,34 @@ struct ColumnRows {
     float sva[ZPL], svb[ZPL];
 };
 
+// A lane's voxel faces: zlo = the lower face's height (a float, exact), and
+// its split zpos = max(zlo, 0), zneg = min(zlo, 0) (one of them is 0).
 template <int ZPL>
-__device__ __forceinline__ void column_load(const ProjParams &P, const float *sino_v, int iu, float ka, float kb,
-                                            const int (&iz)[ZPL], ColumnRows<ZPL> &C)
+struct LaneZ {
+    float zpos[ZPL], zneg[ZPL];
+};
+
+template <int ZPL>
+__device__ __forceinline__ void column_load(const ProjParams &P, const float *sino_v, int iu, float rmin, float rmax,
+                                            const float (&zlo)[ZPL], const LaneZ<ZPL> &L, float c_lo,
+                                            ColumnRows<ZPL> &C)
 {
-    const float hzf = 0.5f * P.nz;
-    // detector row coordinate of height zp: zp * inv_dv + (cv - offv * inv_dv), widened by 1e-3 row
-    const float inv_dv = (float)(1.0 / P.dv);
-    const float c_lo = (float)(0.5 * (P.nv - 1) - P.offv / P.dv) - 1e-3f;
     // sino_v: the view's sinogram; nu * nv < 2^31, so the column offset is 32-bit
     const int coff = iu * P.nv;
     C.srow = row_rsrc(sino_v + coff, P.nv * 4);
     C.irow = row_rsrc(P.imtab + coff, P.nv * 8);
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
-        // rows through [zlo, zhi] within [fa, fb]: zp between z * ka and z * kb
-        const float zlo = iz[k] - hzf;
-        const float zp_lo = fminf(zlo * ka, zlo * kb);
-        C.iva[k] = max((int)ceilf(fmaf(zp_lo, inv_dv, c_lo)), P.iv_lo);
+        // the lowest row through [zlo, zlo + 1] within the piece: zlo * rmin above
+        // z = 0, zlo * rmax below, as two multiply-adds of which one adds an exact
+        // 0; at least the first row that can meet the volume (so the byte offsets
+        // stay >= 0).  c_lo: the row coordinate at z = 0, widened by 1e-3 row.
+        const float rc = fmaf(L.zneg[k], rmax, fmaf(L.zpos[k], rmin, c_lo));
+        C.iva[k] = max((int)ceilf(rc), P.iv_lo);
     }
     // the first two candidate rows of every voxel without a branch.  Reads past a
     // row give 0, and a row outside [iva, ivb] misses the voxel inside the piece, so
-    // its length is <= 0 and adds nothing once clamped at 0.  (Lanes past nz are
-    // never written back.)
+    // its length is 0.  (Lanes past nz are never written back.)
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         C.ima[k] = row_f64(C.irow, C.iva[k]);
@@ -810,24 +825,22 @@ __device__ __forceinline__ void column_load(const ProjParams &P, const float *si
 
 template <int ZPL>
 __device__ __forceinline__ void column_sum(const ProjParams &P, const ColumnRows<ZPL> &C, double sf, float fa,
-                                           float fb, float ka, float kb, const int (&iz)[ZPL],
+                                           float fb, float rmin, float rmax, const float (&zlo)[ZPL],
                                            const double (&klo)[ZPL], float (&vacc)[ZPL])
 {
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
-        const float la = fmaxf(slab_piece(C.ima[k], sf, klo[k], fa, fb), 0.0f);
-        const float lb = fmaxf(slab_piece(C.imb[k], sf, klo[k], fa, fb), 0.0f);
-        float acc_k = fmaf(lb, C.svb[k], fmaf(la, C.sva[k], vacc[k]));
+        const float la = slab_piece_signed(C.ima[k], sf, klo[k], fa, fb);
+        const float lb = slab_piece_signed(C.imb[k], sf, klo[k], fa, fb);
+        float acc_k = fmaf(fabsf(lb), C.svb[k], fmaf(fabsf(la), C.sva[k], vacc[k]));
         if (P.multi_row) {
             // geometries where a ray can meet a voxel in three or more rows: the further candidates
-            const float hzf = 0.5f * P.nz;
-            const float inv_dv = (float)(1.0 / P.dv);
             const float c_hi = (float)(0.5 * (P.nv - 1) - P.offv / P.dv) + 1e-3f;
-            const float zlo = iz[k] - hzf;
-            const float zp_hi = fmaxf(fmaf(zlo, ka, ka), fmaf(zlo, kb, kb));
-            const int ivb = min((int)floorf(fmaf(zp_hi, inv_dv, c_hi)), P.iv_hi);
+            const float zhi = zlo[k] + 1.0f;
+            const float r = zhi >= 0.0f ? rmax : rmin;
+            const int ivb = min((int)floorf(fmaf(zhi, r, c_hi)), P.iv_hi);
             for (int ivr = C.iva[k] + 2; ivr <= ivb; ++ivr) {
-                const float l = slab_piece(row_f64(C.irow, ivr), sf, klo[k], fa, fb);
+                const float l = fabsf(slab_piece_signed(row_f64(C.irow, ivr), sf, klo[k], fa, fb));
                 if (l > 0.0f) acc_k = fmaf(l, row_f32(C.srow, ivr), acc_k);
             }
         }
@@ -837,12 +850,13 @@ __device__ __forceinline__ void column_sum(const ProjParams &P, const ColumnRows
 
 template <int ZPL>
 __device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino_v, int iu, double sf,
-                                              float fa, float fb, float ka, float kb, const int (&iz)[ZPL],
-                                              const double (&klo)[ZPL], float (&vacc)[ZPL])
+                                              float fa, float fb, float rmin, float rmax, const float (&zlo)[ZPL],
+                                              const LaneZ<ZPL> &L, float c_lo, const double (&klo)[ZPL],
+                                              float (&vacc)[ZPL])
 {
     ColumnRows<ZPL> C;
-    column_load<ZPL>(P, sino_v, iu, ka, kb, iz, C);
-    column_sum<ZPL>(P, C, sf, fa, fb, ka, kb, iz, klo, vacc);
+    column_load<ZPL>(P, sino_v, iu, rmin, rmax, zlo, L, c_lo, C);
+    column_sum<ZPL>(P, C, sf, fa, fb, rmin, rmax, zlo, klo, vacc);
 }
 
 // KT = 0: the pieces are computed on the fly (back_mode 1); KT = 2, 3: they
@@ -856,26 +870,37 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int lane = threadIdx.x % WAVE;
     const int64_t t = logical_tile(blockIdx.x, gridDim.x, P.xcd_remap);
-    const int f = (int)(t / P.g_tiles_per_frame);
+    // the tile decode is wave-uniform: keep its results in scalar registers, so
+    // the table and sinogram addresses derived from them stay scalar too
+    const int f = __builtin_amdgcn_readfirstlane((int)(t / P.g_tiles_per_frame));
     int64_t local = t - (int64_t)f * P.g_tiles_per_frame;
     const int nxg = (P.nx + nwaves - 1) / nwaves;
-    const int xg = (int)(local % nxg);
+    const int xg = __builtin_amdgcn_readfirstlane((int)(local % nxg));
     local /= nxg;
-    const int iy = (int)(local % P.ny);
-    const int zc = (int)(local / P.ny);
+    const int iy = __builtin_amdgcn_readfirstlane((int)(local % P.ny));
+    const int zc = __builtin_amdgcn_readfirstlane((int)(local / P.ny));
     const int ix = xg * nwaves + wave;
     if (P.active && !P.active[f]) return;   // the whole workgroup belongs to frame f
     const bool col_ok = ix < P.nx;
     int iz[ZPL];
     double klo[ZPL];
+    float zlo[ZPL];
+    LaneZ<ZPL> L;
     double acc[ZPL];
 #pragma unroll
     for (int k = 0; k < ZPL; ++k) {
         iz[k] = (zc * ZPL + k) * WAVE + lane;
         klo[k] = (double)iz[k] - 0.5 * P.nz;
+        zlo[k] = (float)klo[k];
+        L.zpos[k] = fmaxf(zlo[k], 0.0f);
+        L.zneg[k] = fminf(zlo[k], 0.0f);
         acc[k] = 0.0;
     }
-    const int64_t v0 = col_ok ? P.view_offset[f] : 0, v1 = col_ok ? P.view_offset[f + 1] : 0;
+    // detector row coordinate at z = 0 (row = z * rows-per-z + c), widened by 1e-3 row
+    const float c_lo = (float)(0.5 * (P.nv - 1) - P.offv / P.dv) - 1e-3f;
+    // views of the frame (fewer than 2^31 in all)
+    const int v0 = __builtin_amdgcn_readfirstlane(col_ok ? (int)P.view_offset[f] : 0);
+    const int v1 = __builtin_amdgcn_readfirstlane(col_ok ? (int)P.view_offset[f + 1] : 0);
     const int64_t view_len = (int64_t)P.nu * P.nv;
     if constexpr (KT > 0) {
         const int64_t ncell = (int64_t)P.nx * P.ny;
@@ -891,7 +916,8 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
             // missing b of an odd last pair (reading view a's sinogram).  Both
             // first slots' rows are loaded before either view's sums are taken.
             // Each view keeps its own FP32 sum, and they enter the FP64 sum in
-            // view order, as one view at a time would.
+            // view order, as one view at a time would.  The next pair's table
+            // entries are loaded while the current pair is processed.
             const CellEntry zero{0.0f, 0.0f, 0.0f, 0.0f, 0.0, 0, 0};
             int na_next = 0, nb_next = 0;
             CellEntry ea_next = zero, eb_next = zero;
@@ -903,7 +929,7 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 nb_next = hdr[ncell];
                 eb_next = ent[ncell * KT];
             }
-            for (int64_t v = v0; v < v1; v += 2, sino_v += 2 * view_len) {
+            for (int v = v0; v < v1; v += 2, sino_v += 2 * view_len) {
                 const bool has_b = v + 1 < v1;
                 const int na = na_next, nb = nb_next;
                 const CellEntry ea = ea_next, eb = eb_next;
@@ -930,28 +956,27 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                     vb[k] = 0.0f;
                 }
                 ColumnRows<ZPL> ca, cb;
-                column_load<ZPL>(P, sino_v, ea.iu, ea.ka, ea.kb, iz, ca);
-                column_load<ZPL>(P, sino_b, eb.iu, eb.ka, eb.kb, iz, cb);
-                column_sum<ZPL>(P, ca, ea.sf, ea.fa, ea.fb, ea.ka, ea.kb, iz, klo, va);
-                column_sum<ZPL>(P, cb, eb.sf, eb.fa, eb.fb, eb.ka, eb.kb, iz, klo, vb);
+                column_load<ZPL>(P, sino_v, ea.iu, ea.rmin, ea.rmax, zlo, L, c_lo, ca);
+                column_load<ZPL>(P, sino_b, eb.iu, eb.rmin, eb.rmax, zlo, L, c_lo, cb);
+                column_sum<ZPL>(P, ca, ea.sf, ea.fa, ea.fb, ea.rmin, ea.rmax, zlo, klo, va);
+                column_sum<ZPL>(P, cb, eb.sf, eb.fa, eb.fb, eb.rmin, eb.rmax, zlo, klo, vb);
 #pragma unroll
                 for (int j = 1; j < KT; ++j) {
                     if (j >= na) break;
                     const CellEntry e = ent_a[j];
-                    gather_column<ZPL>(P, sino_v, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, va);
+                    gather_column<ZPL>(P, sino_v, e.iu, e.sf, e.fa, e.fb, e.rmin, e.rmax, zlo, L, c_lo, klo, va);
                 }
 #pragma unroll
                 for (int j = 1; j < KT; ++j) {
                     if (j >= nb) break;
                     const CellEntry e = ent_b[j];
-                    gather_column<ZPL>(P, sino_b, e.iu, e.sf, e.fa, e.fb, e.ka, e.kb, iz, klo, vb);
+                    gather_column<ZPL>(P, sino_b, e.iu, e.sf, e.fa, e.fb, e.rmin, e.rmax, zlo, L, c_lo, klo, vb);
                 }
+                // a missing b (odd last view) has a zero piece: vb is exactly +0
 #pragma unroll
                 for (int k = 0; k < ZPL; ++k) acc[k] += (double)va[k];
-                if (has_b) {
 #pragma unroll
-                    for (int k = 0; k < ZPL; ++k) acc[k] += (double)vb[k];
-                }
+                for (int k = 0; k < ZPL; ++k) acc[k] += (double)vb[k];
             }
         } else {
             // Deeper columns (ZPL > 2) take one view at a time: two views' rows
@@ -964,7 +989,7 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
 #pragma unroll
                 for (int j = 0; j < KT; ++j) e_next[j] = ent[j];
             }
-            for (int64_t v = v0; v < v1; ++v, sino_v += view_len) {
+            for (int v = v0; v < v1; ++v, sino_v += view_len) {
                 const int n = n_next;
                 CellEntry ec[KT];
 #pragma unroll
@@ -982,15 +1007,16 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
 #pragma unroll
                 for (int j = 0; j < KT; ++j) {
                     if (j >= n) break;
-                    gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, ec[j].fa, ec[j].fb, ec[j].ka, ec[j].kb, iz, klo,
-                                       vacc);
+                    gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, ec[j].fa, ec[j].fb, ec[j].rmin, ec[j].rmax,
+                                       zlo, L, c_lo, klo, vacc);
                 }
 #pragma unroll
                 for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
             }
         }
     } else {
-        for (int64_t v = v0; v < v1; ++v) {
+        const float inv_dv = (float)(1.0 / P.dv);
+        for (int v = v0; v < v1; ++v) {
             float vacc[ZPL];
 #pragma unroll
             for (int k = 0; k < ZPL; ++k) vacc[k] = 0.0f;
@@ -1000,10 +1026,9 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
             iu1 = __builtin_amdgcn_readfirstlane(iu1);
             for (int iu = iu0; iu <= iu1; ++iu) {
                 const ColEntry &E = P.cols[v * P.nu + iu];
-                float fa, fb, ka, kb;
-                if (!cell_piece(E, ix, iy, fa, fb, ka, kb)) continue;
-                gather_column<ZPL>(P, sino + v * view_len, iu, E.sf, fa, fb,
-                                   ka, kb, iz, klo, vacc);
+                float fa, fb, rmin, rmax;
+                if (!cell_piece(E, ix, iy, inv_dv, fa, fb, rmin, rmax)) continue;
+                gather_column<ZPL>(P, sino + v * view_len, iu, E.sf, fa, fb, rmin, rmax, zlo, L, c_lo, klo, vacc);
             }
 #pragma unroll
             for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
