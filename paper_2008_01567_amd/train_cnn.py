@@ -90,13 +90,15 @@ def main(argv=None):
     iters = []
     for s in range(args.problems):
         v, y, lam = make_problem(cfg, geom, plan, 40000 + s, dev)
+        if geom.n_vox >= 1 << 24:
+            log("problem %d/%d: inputs ready (%.0fs)" % (s, args.problems, time.perf_counter() - t0))
         g = plan.features(v, y, lam, cfg.sigma)
         x, st = plan.prox_solve(v, y, lam, cfg.sigma, tol=args.target_tol, max_iter=4000, check_every=16)
         V.append(v)
         G.append(g)
         T.append(x.clone())
         iters.append(int(st["iters"].max()))
-        if s % 10 == 0:
+        if s % 10 == 0 or geom.n_vox >= 1 << 24:
             log("problem %d/%d: target CG iterations %s (%.0fs)" % (s, args.problems, st["iters"].max(),
                                                                        time.perf_counter() - t0))
     V, G, T = torch.cat(V), torch.cat(G), torch.cat(T)      # [frames][nz][ny][nx]
@@ -137,6 +139,7 @@ def main(argv=None):
     tol = FROZEN_TOL.get(args.config, cfg.tol)
     evals = []
     for s in range(args.eval):
+        log("evaluation problem %d: generating inputs" % s)
         v, y, lam = make_problem(cfg, geom, plan, 50000 + s, dev)
         _, sp = plan.prox_solve(v, y, lam, cfg.sigma, tol=tol, max_iter=6000, check_every=16)
         _, sl = plan.prox_solve(v, y, lam, cfg.sigma, tol=tol, max_iter=6000, check_every=16, cnn=net)
