@@ -106,7 +106,17 @@ typedef struct msf_solve_opts {
     int32_t x0_mode;             /* MSF_X0_V: start from v; MSF_X0_USER: from x0; MSF_X0_CNN: from cnn */
     int32_t use_graph;           /* 1: replay each CG step as one captured hipGraph */
     int32_t true_residual;       /* 1: recompute ||b - H x|| / ||b|| at the end (one more A, A^T) */
-    int32_t reserved;
+    int32_t refine_every;        /* 0: off.  k > 0: iterative refinement.  At the start, every k CG steps
+                                    (k rounded up to a multiple of check_every), and whenever every frame
+                                    has frozen, the recursive residual is replaced by b - H x computed with
+                                    FP64 ray-voxel lengths, an FP64 sinogram and FP64 sums, and each
+                                    frame's CG restarts from it (p = r).  Between replacements CG freezes a
+                                    frame at 0.1 tol on its recursive residual; a frame is accepted only
+                                    when the FP64 residual meets tol (or at max_iter), and the status and
+                                    converged flags judge that residual.  For stiff systems (large Lambda)
+                                    whose error sits far above what the FP32 projector's rounding allows.
+                                    Uses one FP64 sinogram of plan workspace (allocated on first use).
+                                    true_rel_residual then reports the last FP64 residual. */
     const float *x0;             /* device [n_frames][nz][ny][nx], MSF_X0_USER only */
     const msf_cnn *cnn;          /* MSF_X0_CNN only */
 } msf_solve_opts;
@@ -124,7 +134,7 @@ typedef struct msf_solve_stats {
 } msf_solve_stats;
 
 /* Fill *opts with defaults: tol 1e-6, max_iter 1000, check_every 8, start from v,
- * graphs on, no true residual. */
+ * graphs on, no true residual, no refinement. */
 void msf_solve_opts_default(msf_solve_opts *opts);
 
 /* Create a plan for one geometry: validates it (EINVAL on non-positive sizes

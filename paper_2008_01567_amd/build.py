@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsf.so")
-SOURCES = ["capi.hip", "projector.hip", "cg.hip", "cnn.hip", "mace.hip", "fixture.hip"]
+SOURCES = ["capi.hip", "projector.hip", "cg.hip", "cnn.hip", "mace.hip", "fixture.hip", "exact.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

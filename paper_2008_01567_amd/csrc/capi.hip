@@ -31,7 +31,7 @@ void free_plan_memory(msf_plan *P)
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     P->graph = nullptr;
     P->graph_valid = false;
-    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_imtab, P->d_cell_hdr, P->d_cell_ent, P->d_walk_head, P->d_walk_ent, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->vin,
+    void *ptrs[] = {P->d_cs, P->d_rzp, P->d_imtab, P->d_cell_hdr, P->d_cell_ent, P->d_walk_head, P->d_walk_ent, P->d_scale, P->part_g, P->d_cols, P->d_view_offset, P->d_tile_offset, P->x, P->r, P->p, P->bp, P->z64, P->x64, P->vin,
                     P->sy, P->slam, P->sz, P->part_proj, P->part_vol, P->scal, P->iscal, P->consts,
                     P->flags};
     for (void *q : ptrs)
@@ -598,15 +598,17 @@ namespace {
 // Transposes and checks the inputs, then computes ||b|| and r = b - H x for the
 // chosen start (v or a caller's x0).  Validation finishes before anything is
 // written to caller memory.
+// tol: the recursive residual at which CG steps freeze a frame; tol_final:
+// the FP64 residual at which a refined solve accepts it (refinement only).
 msf_status prepare(msf_plan *P, const float *v, const float *y, const float *lam, double sigma, double tol,
-                   int max_iter, const float *x0_user, hipStream_t s)
+                   int max_iter, const float *x0_user, hipStream_t s, double tol_final = 0.0)
 {
     double *hc = (double *)P->host_stage;
     int32_t *hflags = (int32_t *)(hc + 4);
     hc[0] = 1.0 / (sigma * sigma);
     hc[1] = tol;
     hc[2] = (double)max_iter;
-    hc[3] = 0.0;
+    hc[3] = tol_final;
     HIPCHK(hipMemcpyAsync(P->consts, hc, 4 * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(P->flags, 0, 4 * sizeof(int32_t), s));
     HIPCHK(vol_to_internal(*P, v, P->vin, 1, P->flags + 2, s));
@@ -657,6 +659,33 @@ msf_status feature(msf_plan *P, hipStream_t s)
     return MSF_OK;
 }
 
+// Iterative refinement.  The iterate is x64 (FP64); the FP32 vector x holds
+// the correction that the CG steps since the last refinement have built.
+// Each refinement adds that correction to x64 and zeroes x, computes
+// r = b - H x64 with the FP64 operator (exact.hip), and restarts every
+// frame's CG from it (p = r), so the following FP32 steps solve for the next
+// correction.  A frame is then active unless that residual meets the final
+// tolerance or its steps are used up.  (Keeping the old direction across a
+// replacement of the residual diverges on the stiff systems this is for: the
+// FP32 and FP64 operators differ too much relative to the late residuals.)
+// first: x64 = x (the start) instead of a fold.
+msf_status refine_residual(msf_plan *P, bool first, hipStream_t s)
+{
+    if (!P->z64) {
+        int64_t bytes = 0;
+        hipError_t e = dalloc(&P->z64, (size_t)std::max<int64_t>(P->nmeas_total, 1), bytes);
+        if (e == hipSuccess) e = dalloc(&P->x64, (size_t)std::max<int64_t>(P->nvox_total, 1), bytes);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc refinement workspace");
+        P->workspace_bytes += bytes;
+    }
+    if (first) HIPCHK(launch_fill_d(P->x64, P->nvox_total, s));
+    HIPCHK(launch_fold_correction(*P, s));
+    HIPCHK(launch_exact_data_residual(*P, P->x64, P->z64, s));
+    HIPCHK(launch_vol_residual64(*P, s));
+    HIPCHK(launch_scalar_reduce(*P, RW_REPLACE, s));
+    return MSF_OK;
+}
+
 }  // namespace
 
 msf_status msf_prox_features(msf_plan *P, const float *v, const float *y, const float *lam, double sigma, float *g_out,
@@ -684,8 +713,9 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
     msf_solve_opts o;
     if (opts_in) o = *opts_in;
     else msf_solve_opts_default(&o);
-    if (!(std::isfinite(o.tol) && o.tol >= 0.0) || o.max_iter < 0 || o.check_every < 1) {
-        set_error("invalid solver options (tol >= 0, max_iter >= 0, check_every >= 1)"); return MSF_EINVAL;
+    if (!(std::isfinite(o.tol) && o.tol >= 0.0) || o.max_iter < 0 || o.check_every < 1 || o.refine_every < 0) {
+        set_error("invalid solver options (tol >= 0, max_iter >= 0, check_every >= 1, refine_every >= 0)");
+        return MSF_EINVAL;
     }
     if (o.x0_mode == MSF_X0_USER && !o.x0) { set_error("x0_mode USER needs x0"); return MSF_EINVAL; }
     if (o.x0_mode == MSF_X0_CNN && (!o.cnn || cnn_kind(o.cnn) != MSF_CNN_WARM_START)) {
@@ -697,7 +727,11 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
     }
     hipStream_t s = (hipStream_t)stream;
     const int nf = P->nf;
-    msf_status pst = prepare(P, v, y, lam, sigma, o.tol, o.max_iter, o.x0_mode == MSF_X0_USER ? o.x0 : nullptr, s);
+    // With refinement the FP32 steps of each correction run to a tenth of tol
+    // on their recursive residual; the FP64 residual decides at tol.
+    const bool refine = o.refine_every > 0;
+    msf_status pst = prepare(P, v, y, lam, sigma, refine ? 0.1 * o.tol : o.tol, o.max_iter,
+                             o.x0_mode == MSF_X0_USER ? o.x0 : nullptr, s, o.tol);
     if (pst != MSF_OK) return pst;
     int32_t *hflags = (int32_t *)((double *)P->host_stage + 4);
 
@@ -764,10 +798,31 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
     int32_t *hact = hflags;
     int steps = 0;
     std::vector<float> step_fwd_ms, step_back_ms;
-    HIPCHK(hipMemcpyAsync(hact, P->iscal + IS_ACTIVE * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    auto fetch_active = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(hact, P->iscal + IS_ACTIVE * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost,
+                                      s);
+        return e == hipSuccess ? hipStreamSynchronize(s) : e;
+    };
+    const int refine_period = refine ? ((o.refine_every + period - 1) / period) * period : 0;
+    int since_refine = 0;
+    if (refine) {
+        // the start becomes the FP64 iterate; its residual with the FP64 operator
+        msf_status rs = refine_residual(P, true, s);
+        if (rs != MSF_OK) return rs;
+    }
+    HIPCHK(fetch_active());
     bool any = std::any_of(hact, hact + nf, [](int32_t a) { return a != 0; });
-    while (any && steps < o.max_iter) {
+    while (steps < o.max_iter) {
+        if (!any) {
+            if (!refine || since_refine == 0) break;
+            // every frame met tol on its recursive residual: confirm with the FP64 one
+            msf_status rs = refine_residual(P, false, s);
+            if (rs != MSF_OK) return rs;
+            since_refine = 0;
+            HIPCHK(fetch_active());
+            any = std::any_of(hact, hact + nf, [](int32_t a) { return a != 0; });
+            continue;
+        }
         const int n = std::min(period, o.max_iter - steps);
         if (use_graph && n == period) {
             HIPCHK(hipGraphLaunch(P->graph, s));
@@ -775,8 +830,13 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
             for (int k = 0; k < n; ++k) HIPCHK(launch_cg_step(*P, s, P->timing ? &P->ev[4 * k] : nullptr));
         }
         steps += n;
-        HIPCHK(hipMemcpyAsync(hact, P->iscal + IS_ACTIVE * nf, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        since_refine += n;
+        if (refine && since_refine >= refine_period && steps < o.max_iter) {
+            msf_status rs = refine_residual(P, false, s);
+            if (rs != MSF_OK) return rs;
+            since_refine = 0;
+        }
+        HIPCHK(fetch_active());
         if (P->timing) {
             for (int k = 0; k < n; ++k) {
                 float a = 0.0f, b = 0.0f;
@@ -789,8 +849,19 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
         any = std::any_of(hact, hact + nf, [](int32_t a) { return a != 0; });
     }
 
+    if (refine) {
+        // steps since the last refinement (max_iter reached): fold them in and
+        // report the FP64 residual of the final iterate; then x = x64 in FP32
+        if (since_refine > 0) {
+            HIPCHK(launch_fold_correction(*P, s));
+            HIPCHK(launch_exact_data_residual(*P, P->x64, P->z64, s));
+            HIPCHK(launch_vol_residual64(*P, s));
+            HIPCHK(launch_scalar_reduce(*P, RW_TRUE, s));
+        }
+        HIPCHK(launch_d2f(P->x64, P->x, P->nvox_total, s));
+    }
     HIPCHK(vol_to_public(*P, P->x, x_out, s));
-    if (o.true_residual) {
+    if (o.true_residual && !refine) {
         HIPCHK(launch_forward(*P, PM_RESID, P->x, P->sy, P->sz, false, s));
         HIPCHK(launch_back(*P, P->sz, P->bp, false, s));
         HIPCHK(launch_vol_true_residual(*P, s));
@@ -805,13 +876,16 @@ msf_status msf_prox_solve(msf_plan *P, const float *v, const float *y, const flo
     msf_status st = MSF_OK;
     for (int f = 0; f < nf; ++f) {
         const double rel = hs[SC_REL * nf + f];
-        const bool conv = hs[SC_BNORM * nf + f] > 0.0 ? rel <= o.tol : hs[SC_GAMMA * nf + f] == 0.0;
+        // refined solves are judged by their final FP64 residual
+        const double judged = refine ? hs[SC_TRUE * nf + f] : rel;
+        const bool conv = hs[SC_BNORM * nf + f] > 0.0 ? judged <= o.tol : hs[SC_GAMMA * nf + f] == 0.0;
         if (hi[IS_STATUS * nf + f] == MSF_EBREAKDOWN) st = MSF_EBREAKDOWN;
         else if (!conv && st == MSF_OK) st = MSF_NOT_CONVERGED;
         if (stats) {
             if (stats->iters) stats->iters[f] = hi[IS_ITERS * nf + f];
             if (stats->rel_residual) stats->rel_residual[f] = rel;
-            if (stats->true_rel_residual) stats->true_rel_residual[f] = o.true_residual ? hs[SC_TRUE * nf + f] : -1.0;
+            if (stats->true_rel_residual)
+                stats->true_rel_residual[f] = (o.true_residual || refine) ? hs[SC_TRUE * nf + f] : -1.0;
             if (stats->converged) stats->converged[f] = conv ? 1 : 0;
             if (stats->cnn_used) stats->cnn_used[f] = o.x0_mode == MSF_X0_CNN ? (uint8_t)hi[IS_CNN * nf + f] : 0;
             if (stats->start_rel_residual) stats->start_rel_residual[f] = rel0[f];

@@ -117,6 +117,7 @@ unsigned grid_for(int64_t n)
 struct VolArgs {
     float *x, *r, *p;
     double *bp;
+    double *x64;             // FP64 iterate of a refined solve (or null)
     const float *vin;
     double *part;            // [nf * bpf]
     const double *scal;      // [SC_COUNT][nf]
@@ -227,6 +228,44 @@ __global__ __launch_bounds__(VB) void k_vol_select(VolArgs A, const int32_t *use
     if (threadIdx.x == 0) A.part[(int64_t)f * A.bpf + blockIdx.x] = s;
 }
 
+// Iterative refinement: fold the FP32 correction into the FP64 iterate.
+__global__ __launch_bounds__(VB) void k_fold(VolArgs A)
+{
+    const int f = blockIdx.y;
+    const int64_t base = (int64_t)f * A.nvox;
+    for (int k = 0; k < VE; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
+        if (i < A.nvox) {
+            A.x64[base + i] += (double)A.x[base + i];
+            A.x[base + i] = 0.0f;
+        }
+    }
+}
+
+// Iterative refinement: r = p = bp + (v - x64) / sigma^2 (bp the FP64
+// A^T Lambda (y - A x64)), the residual of the FP64 iterate, rounded once to
+// FP32; partial ||r||^2 of the rounded values; clears bp.
+__global__ __launch_bounds__(VB) void k_vol_residual64(VolArgs A)
+{
+    const int f = blockIdx.y;
+    const double is2 = A.consts[0];
+    const int64_t base = (int64_t)f * A.nvox;
+    double s = 0.0;
+    for (int k = 0; k < VE; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
+        if (i < A.nvox) {
+            const double rv = A.bp[base + i] + ((double)A.vin[base + i] - A.x64[base + i]) * is2;
+            const float rf = (float)rv;
+            A.r[base + i] = rf;
+            A.p[base + i] = rf;
+            s += (double)rf * (double)rf;
+            A.bp[base + i] = 0.0;
+        }
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) A.part[(int64_t)f * A.bpf + blockIdx.x] = s;
+}
+
 // x += alpha p;  r -= alpha (bp + p / sigma^2);  bp = 0;  partial ||r||^2.
 __global__ __launch_bounds__(VB) void k_update_xr(VolArgs A)
 {
@@ -330,6 +369,16 @@ __global__ __launch_bounds__(VB) void k_red_setup(ScalArgs A, int what)
     } else if (what == RW_TRUE) {
         const double bn = S(A, SC_BNORM, f);
         S(A, SC_TRUE, f) = bn > 0.0 ? sqrt(s) / bn : sqrt(s);
+    } else if (what == RW_REPLACE) {
+        // the recursive residual replaced by the FP64 one, CG restarted from it (p = r)
+        const double bn = S(A, SC_BNORM, f);
+        const double rel = bn > 0.0 ? sqrt(s) / bn : sqrt(s);
+        S(A, SC_GAMMA, f) = s;
+        S(A, SC_PP, f) = s;
+        S(A, SC_REL, f) = rel;
+        S(A, SC_TRUE, f) = rel;
+        const bool done = (bn > 0.0 ? rel <= A.consts[3] : s == 0.0) || I(A, IS_ITERS, f) >= (int)A.consts[2];
+        if (I(A, IS_STATUS, f) != MSF_EBREAKDOWN) I(A, IS_ACTIVE, f) = done ? 0 : 1;
     } else if (what == RW_DIAG) {
         // mean of A^T Lambda A 1 over the frame's voxels, plus the 1/sigma^2 of H
         S(A, SC_DIAG, f) = s / (double)A.nvox + A.consts[0];
@@ -393,7 +442,7 @@ __global__ __launch_bounds__(VB) void k_red_beta(ScalArgs A)
 VolArgs vol_args(msf_plan &P, bool with_active)
 {
     VolArgs A;
-    A.x = P.x; A.r = P.r; A.p = P.p; A.bp = P.bp; A.vin = P.vin;
+    A.x = P.x; A.r = P.r; A.p = P.p; A.bp = P.bp; A.x64 = P.x64; A.vin = P.vin;
     A.part = P.part_vol;
     A.scal = P.scal;
     A.active = with_active ? P.iscal + IS_ACTIVE * P.nf : nullptr;
@@ -510,6 +559,18 @@ hipError_t launch_scale_feature(msf_plan &P, hipStream_t s)
 hipError_t launch_vol_residual_p(msf_plan &P, hipStream_t s)
 {
     hipLaunchKernelGGL(k_vol_residual, vol_grid(P), dim3(VB), 0, s, vol_args(P, false), 2);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_correction(msf_plan &P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold, vol_grid(P), dim3(VB), 0, s, vol_args(P, false));
+    return hipGetLastError();
+}
+
+hipError_t launch_vol_residual64(msf_plan &P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vol_residual64, vol_grid(P), dim3(VB), 0, s, vol_args(P, false));
     return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -107,7 +108,8 @@ enum ScalarSlot : int {
     SC_COUNT
 };
 enum IScalarSlot : int { IS_ACTIVE = 0, IS_ITERS, IS_STATUS, IS_CNN, IS_COUNT };
-// global solve constants live in consts[]: [0] = 1/sigma^2, [1] = tol, [2] = max_iter
+// global solve constants live in consts[]: [0] = 1/sigma^2, [1] = tol of the recursive residual,
+// [2] = max_iter, [3] = tol of the FP64 residual (refinement)
 
 struct msf_plan {
     // geometry (host copy)
@@ -142,6 +144,8 @@ struct msf_plan {
     // device workspace
     float *x = nullptr, *r = nullptr, *p = nullptr, *vin = nullptr;
     double *bp = nullptr;         // backprojection accumulator (FP64 atomic adds)
+    double *z64 = nullptr;        // FP64 sinogram of the refinement residual (allocated on first use)
+    double *x64 = nullptr;        // FP64 iterate of a refined solve (allocated with z64)
     float *sy = nullptr, *slam = nullptr, *sz = nullptr;
     double *part_proj = nullptr;  // [total_tiles]
     double *part_vol = nullptr;   // [nf * vol_blocks_per_frame]
@@ -226,7 +230,15 @@ enum ReduceWhat : int {
     RW_TRUE = 2,       // part_vol -> SC_TRUE
     RW_DIAG = 3,       // part_vol (sum of A^T Lambda A 1) -> SC_DIAG
     RW_CNN = 4,        // part_vol -> SC_GCNN, then choose the start per frame (IS_CNN)
+    RW_REPLACE = 5,    // part_vol of the FP64 residual (CG restarted from it) -> SC_GAMMA, SC_PP, SC_REL,
+                       // SC_TRUE, active flags (iteration counts kept)
 };
+// bp = A^T Lambda (y - A x) with FP64 lengths, sinogram (z64) and sums, x an FP64 volume (exact.hip)
+hipError_t launch_exact_data_residual(msf_plan &P, const double *x, double *z64, hipStream_t s);
+// refinement: x64 += x (the FP32 correction), x = 0
+hipError_t launch_fold_correction(msf_plan &P, hipStream_t s);
+// refinement: r = p = bp + (v - x64) / sigma^2, partial ||r||^2 into part_vol; clears bp
+hipError_t launch_vol_residual64(msf_plan &P, hipStream_t s);
 hipError_t launch_vol_sum_bp(msf_plan &P, hipStream_t s);
 // p = r / diag_f (the network's residual feature, internal layout)
 hipError_t launch_scale_feature(msf_plan &P, hipStream_t s);

@@ -46,7 +46,7 @@ class msf_tiles(C.Structure):
 class msf_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("x0_mode", C.c_int32), ("use_graph", C.c_int32), ("true_residual", C.c_int32),
-                ("reserved", C.c_int32), ("x0", C.c_void_p), ("cnn", C.c_void_p)]
+                ("refine_every", C.c_int32), ("x0", C.c_void_p), ("cnn", C.c_void_p)]
 
 
 class msf_solve_stats(C.Structure):
@@ -289,7 +289,7 @@ class Plan:
         return out, {"status": status, "cg_iters": it[:n_iter], "cg_total": st.cg_total, "seconds": st.seconds}
 
     def prox_solve(self, v, y, lam, sigma, tol=1e-6, max_iter=1000, check_every=8, x0=None, use_graph=True,
-                   true_residual=False, out=None, stream=None, cnn=None):
+                   true_residual=False, out=None, stream=None, cnn=None, refine_every=0):
         """Returns (x, stats) with stats a dict of per-frame arrays and the status code."""
         import torch
         nf = self.geom.n_frames
@@ -299,6 +299,7 @@ class Plan:
         lib().msf_solve_opts_default(C.byref(o))
         o.tol, o.max_iter, o.check_every = float(tol), int(max_iter), int(check_every)
         o.use_graph, o.true_residual = int(bool(use_graph)), int(bool(true_residual))
+        o.refine_every = int(refine_every)
         if x0 is not None:
             o.x0_mode = MSF_X0_USER
             o.x0 = _ptr(x0, self.n_vox).value

@@ -47,7 +47,7 @@ def test_oracle_under_asan_ubsan(tmp_path):
 def test_c_abi_validation_under_asan_ubsan(tmp_path):
     lib = str(tmp_path / "libmsf_asan.so")
     srcs = [os.path.join(CSRC, s) for s in ("capi.hip", "projector.hip", "cg.hip", "cnn.hip", "mace.hip",
-                                            "fixture.hip")]
+                                            "fixture.hip", "exact.hip")]
     # host code instrumented (-Xarch_host before each sanitizer flag), device code built as usual
     cmd = [HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
