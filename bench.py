@@ -43,12 +43,12 @@ VALU_OPS_PER_INTERSECTION = 12
 # kernel of known size in the same run (read x2.0, write x1.0).  Valid only
 # for the projector source and launch shape they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "ae8489e4fe68ac2e2fff7d340d4c1afe2d7a7a84ebaeda02f6647dab8c4a1399",
+    "source_sha256": "ec0472034720213782fd034db00c6bc1eece63726800c4c95f018f23908c02ea",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
     "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.4e6,
     "read_bytes": 987.4e6, "write_bytes": 265.0e6, "l2_hit_rate": 0.933,
     # SQ_INSTS_VALU x 64 / nnz(A) of the same runs: VALU lane-instructions per intersection
-    "valu_lane_instr_per_intersection": 30.4,
+    "valu_lane_instr_per_intersection": 27.1,
     "profile": "profiles/gather_update_c2_128x16_counters.md",
 }
 

@@ -823,7 +823,10 @@ __device__ __forceinline__ void column_load(const ProjParams &P, const float *si
     }
 }
 
-template <int ZPL>
+// MR = false: the plan's bound says no ray meets one voxel inside one piece in
+// three or more rows, and the path for rows past the first two is not compiled;
+// MR = true keeps it behind the plan's run-time flag.
+template <int ZPL, bool MR>
 __device__ __forceinline__ void column_sum(const ProjParams &P, const ColumnRows<ZPL> &C, double sf, float fa,
                                            float fb, float rmin, float rmax, const float (&zlo)[ZPL],
                                            const double (&klo)[ZPL], float (&vacc)[ZPL])
@@ -833,7 +836,7 @@ __device__ __forceinline__ void column_sum(const ProjParams &P, const ColumnRows
         const float la = slab_piece_signed(C.ima[k], sf, klo[k], fa, fb);
         const float lb = slab_piece_signed(C.imb[k], sf, klo[k], fa, fb);
         float acc_k = fmaf(fabsf(lb), C.svb[k], fmaf(fabsf(la), C.sva[k], vacc[k]));
-        if (P.multi_row) {
+        if (MR && P.multi_row) {
             // geometries where a ray can meet a voxel in three or more rows: the further candidates
             const float c_hi = (float)(0.5 * (P.nv - 1) - P.offv / P.dv) + 1e-3f;
             const float zhi = zlo[k] + 1.0f;
@@ -848,7 +851,7 @@ __device__ __forceinline__ void column_sum(const ProjParams &P, const ColumnRows
     }
 }
 
-template <int ZPL>
+template <int ZPL, bool MR>
 __device__ __forceinline__ void gather_column(const ProjParams &P, const float *sino_v, int iu, double sf,
                                               float fa, float fb, float rmin, float rmax, const float (&zlo)[ZPL],
                                               const LaneZ<ZPL> &L, float c_lo, const double (&klo)[ZPL],
@@ -856,13 +859,13 @@ __device__ __forceinline__ void gather_column(const ProjParams &P, const float *
 {
     ColumnRows<ZPL> C;
     column_load<ZPL>(P, sino_v, iu, rmin, rmax, zlo, L, c_lo, C);
-    column_sum<ZPL>(P, C, sf, fa, fb, rmin, rmax, zlo, klo, vacc);
+    column_sum<ZPL, MR>(P, C, sf, fa, fb, rmin, rmax, zlo, klo, vacc);
 }
 
 // KT = 0: the pieces are computed on the fly (back_mode 1); KT = 2, 3: they
 // come from the cell table with KT slots per (view, cell) (back_mode 2), the
 // next view's entries loaded while the current view is processed.
-template <int ZPL, bool FUSED, int KT>
+template <int ZPL, bool FUSED, int KT, bool MR>
 __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const float *__restrict__ sino,
                                                      double *__restrict__ out, const GatherUpdate U)
 {
@@ -958,19 +961,19 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 ColumnRows<ZPL> ca, cb;
                 column_load<ZPL>(P, sino_v, ea.iu, ea.rmin, ea.rmax, zlo, L, c_lo, ca);
                 column_load<ZPL>(P, sino_b, eb.iu, eb.rmin, eb.rmax, zlo, L, c_lo, cb);
-                column_sum<ZPL>(P, ca, ea.sf, ea.fa, ea.fb, ea.rmin, ea.rmax, zlo, klo, va);
-                column_sum<ZPL>(P, cb, eb.sf, eb.fa, eb.fb, eb.rmin, eb.rmax, zlo, klo, vb);
+                column_sum<ZPL, MR>(P, ca, ea.sf, ea.fa, ea.fb, ea.rmin, ea.rmax, zlo, klo, va);
+                column_sum<ZPL, MR>(P, cb, eb.sf, eb.fa, eb.fb, eb.rmin, eb.rmax, zlo, klo, vb);
 #pragma unroll
                 for (int j = 1; j < KT; ++j) {
                     if (j >= na) break;
                     const CellEntry e = ent_a[j];
-                    gather_column<ZPL>(P, sino_v, e.iu, e.sf, e.fa, e.fb, e.rmin, e.rmax, zlo, L, c_lo, klo, va);
+                    gather_column<ZPL, MR>(P, sino_v, e.iu, e.sf, e.fa, e.fb, e.rmin, e.rmax, zlo, L, c_lo, klo, va);
                 }
 #pragma unroll
                 for (int j = 1; j < KT; ++j) {
                     if (j >= nb) break;
                     const CellEntry e = ent_b[j];
-                    gather_column<ZPL>(P, sino_b, e.iu, e.sf, e.fa, e.fb, e.rmin, e.rmax, zlo, L, c_lo, klo, vb);
+                    gather_column<ZPL, MR>(P, sino_b, e.iu, e.sf, e.fa, e.fb, e.rmin, e.rmax, zlo, L, c_lo, klo, vb);
                 }
                 // a missing b (odd last view) has a zero piece: vb is exactly +0
 #pragma unroll
@@ -1007,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
 #pragma unroll
                 for (int j = 0; j < KT; ++j) {
                     if (j >= n) break;
-                    gather_column<ZPL>(P, sino_v, ec[j].iu, ec[j].sf, ec[j].fa, ec[j].fb, ec[j].rmin, ec[j].rmax,
+                    gather_column<ZPL, MR>(P, sino_v, ec[j].iu, ec[j].sf, ec[j].fa, ec[j].fb, ec[j].rmin, ec[j].rmax,
                                        zlo, L, c_lo, klo, vacc);
                 }
 #pragma unroll
@@ -1028,7 +1031,7 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
                 const ColEntry &E = P.cols[v * P.nu + iu];
                 float fa, fb, rmin, rmax;
                 if (!cell_piece(E, ix, iy, inv_dv, fa, fb, rmin, rmax)) continue;
-                gather_column<ZPL>(P, sino + v * view_len, iu, E.sf, fa, fb, rmin, rmax, zlo, L, c_lo, klo, vacc);
+                gather_column<ZPL, MR>(P, sino + v * view_len, iu, E.sf, fa, fb, rmin, rmax, zlo, L, c_lo, klo, vacc);
             }
 #pragma unroll
             for (int k = 0; k < ZPL; ++k) acc[k] += (double)vacc[k];
@@ -1174,11 +1177,23 @@ template <bool FUSED, int KT>
 void gather_dispatch(int zpl, dim3 grid, dim3 block, hipStream_t s, const ProjParams &pp, const float *sino,
                      double *out, const GatherUpdate &U)
 {
+    // Columns of up to 2 voxels per lane drop the third-row path when the plan's
+    // bound allows (fewer registers, no hoisted row bound; 794 -> 776 us at
+    // 128^3 x 16).  The deeper columns keep it behind the run-time flag: compiled
+    // without it they run at 7 waves per SIMD instead of 5 and take 1-3% longer
+    // (256^3 and 512 x 512 x 256), with the occupancy capped at 5 or 6 as well.
+    const bool lean = !pp.multi_row;
     switch (zpl) {
-    case 1: hipLaunchKernelGGL((k_back_gather<1, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
-    case 2: hipLaunchKernelGGL((k_back_gather<2, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
-    case 3: hipLaunchKernelGGL((k_back_gather<3, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
-    default: hipLaunchKernelGGL((k_back_gather<4, FUSED, KT>), grid, block, 0, s, pp, sino, out, U); break;
+    case 1:
+        if (lean) hipLaunchKernelGGL((k_back_gather<1, FUSED, KT, false>), grid, block, 0, s, pp, sino, out, U);
+        else hipLaunchKernelGGL((k_back_gather<1, FUSED, KT, true>), grid, block, 0, s, pp, sino, out, U);
+        break;
+    case 2:
+        if (lean) hipLaunchKernelGGL((k_back_gather<2, FUSED, KT, false>), grid, block, 0, s, pp, sino, out, U);
+        else hipLaunchKernelGGL((k_back_gather<2, FUSED, KT, true>), grid, block, 0, s, pp, sino, out, U);
+        break;
+    case 3: hipLaunchKernelGGL((k_back_gather<3, FUSED, KT, true>), grid, block, 0, s, pp, sino, out, U); break;
+    default: hipLaunchKernelGGL((k_back_gather<4, FUSED, KT, true>), grid, block, 0, s, pp, sino, out, U); break;
     }
 }
 
