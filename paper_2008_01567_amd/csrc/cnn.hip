@@ -16,9 +16,13 @@
 //
 // Every layer is an implicit GEMM on the matrix cores: channels-last BF16
 // activations [N][Z][Y][X][16] (the 2- or 5-channel input and the 1-channel
-// output are zero-padded to 16), and for each tap one
-// v_mfma_f32_16x16x16_bf16 multiplies the tap's 16 x 16 weight block by 16
-// voxels x 16 input channels, accumulating in FP32.  Input rows are staged in
+// output are zero-padded to 16), and each v_mfma_f32_16x16x32_bf16 multiplies
+// 16 output channels by 16 voxels over K = 32 (tap, input channel) pairs,
+// accumulating in FP32: two taps of 16 channels each, or, where only the
+// first 8 channels can be nonzero (the denoiser's first layer), four taps of
+// 8.  Lane (r, g) of the wave supplies the 8 K values 8g .. 8g + 7 for output
+// channel r (weights) and voxel r (activations), the latter with one 16-byte
+// LDS read.  Input rows are staged in
 // LDS by workgroup tiles (2D images: row tiles; 3D volumes: row tiles sliding
 // along z with a three-slice ring), zero outside the volume.  The input gradient is
 // the same kernel run with the spatially flipped, channel-transposed weights;
@@ -33,6 +37,8 @@
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -171,6 +177,41 @@ constexpr int TY = 8, TXW = 64, TROW = TXW + 2;
 constexpr int TILE_U4 = (TY + 2) * TROW * 2;          // 16-byte chunks in the staged rows
 constexpr int TILE_LD = (TILE_U4 + 255) / 256;        // per thread
 
+// 8 BF16 values at a 16-byte aligned v4s pair (weights or staged channels)
+__device__ __forceinline__ v8bf ld8(const v4s *p) { return __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(p)); }
+
+// The K slots of one 16x16x32 MFMA over a 3x3 window: TPM taps of 32 / TPM
+// channels each (TPM = 2: all 16 channels; TPM = 4: channels 0 .. 7).  Lane
+// group g takes tap TPM m + g / (4 / TPM) of MFMA m and channel block
+// c = (g % (4 / TPM)) * 8; taps past the window get zero weights (and read
+// tap 0's voxel, a finite value).  For tap (dy, dx) the staged voxel of output
+// column r is at (dy * TROW + dx + r) * 4 + c / 4 in v4s units.
+template <int TPM>
+struct Window {
+    static constexpr int M = (9 + TPM - 1) / TPM;   // MFMAs per output row
+    v8bf w[M];
+    int off[M];
+    __device__ __forceinline__ void load(const v4s *wl, int tap0, int r, int g)
+    {
+        constexpr int per = 4 / TPM;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int tap = TPM * m + g / per, c4 = (g % per) * 2;
+            const bool real = tap < 9;
+            const v8bf zero = {};
+            w[m] = real ? ld8(wl + (tap0 + (real ? tap : 0)) * (CH * 4) + r * 4 + c4) : zero;
+            off[m] = real ? ((tap / 3) * TROW + tap % 3) * 4 + c4 : c4;
+        }
+    }
+    // acc += this window applied at staged position base (v4s units, column r included)
+    __device__ __forceinline__ void apply(const v4s *tl, int base, v4f &acc) const
+    {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[m], ld8(tl + base + off[m]), acc, 0, 0, 0);
+    }
+};
+
 struct TilePos {
     int n, y0, x0;
 };
@@ -266,9 +307,9 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
     if (t >= ntile) return;                  // the whole workgroup
     TilePos p = tile_pos(t, ntx, nty);
     __syncthreads();                         // the weights are staged
-    v4s wr[9];                               // this lane's weight blocks, in registers
-#pragma unroll
-    for (int q = 0; q < 9; ++q) wr[q] = wl[q * (CH * 4) + r * 4 + g];
+    // this lane's weight blocks, in registers; the first layer's inputs fill channels 0 .. 4 only
+    Window<F32IN ? 4 : 2> win;
+    win.load(wl, 0, r, g);
     uint4 reg[F32IN ? 1 : TILE_LD];
     float regf[F32IN ? TILE_VLD : 1][5];
     if constexpr (F32IN) tile_fetch_f32(A, p, regf);
@@ -308,14 +349,8 @@ __global__ __launch_bounds__(256) void k_conv2d(const ConvArgs A)
         }
         for (int ry = 0; ry < TY && pc.y0 + ry < A.Y; ++ry) {
             v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    // staged voxel (row ry + dy, column 16 wave + r + dx), channels 4g .. 4g + 3
-                    const v4s a = tl[((ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[dy * 3 + dx], a, acc, 0, 0, 0);
-                }
+            // staged voxels (row ry + dy, column 16 wave + r + dx)
+            win.apply(tl, (ry * TROW + 16 * wave + r) * 4, acc);
             const int y = pc.y0 + ry, xv = xs + r;
             const int64_t vox = ((int64_t)pc.n * A.Y + y) * A.X + xv;
             if constexpr (EPI == EPI_RESID) {
@@ -398,9 +433,8 @@ __global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int 
     };
     put();
     __syncthreads();                         // the weights are staged
-    v4s wr[9];                               // this lane's weight blocks, in registers
-#pragma unroll
-    for (int q = 0; q < 9; ++q) wr[q] = wl[q * (CH * 4) + r * 4 + g];
+    Window<4> win;                           // channels 0 .. 4 carry the input: four taps per MFMA
+    win.load(wl, 0, r, g);
     const v4s *tl = reinterpret_cast<const v4s *>(tile);
     for (int t = t0; t < t1; ++t) {
         __syncthreads();                     // the channels of time point t are staged
@@ -410,14 +444,7 @@ __global__ __launch_bounds__(256) void k_conv2d_first_seq(const ConvArgs A, int 
             const int64_t n = (int64_t)t * S + si - (int64_t)A.pin.n0;     // image within the chunk
             for (int ry = 0; ry < TY && y0 + ry < A.Y; ++ry) {
                 v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) {
-                        // staged voxel (row ry + dy, column 16 wave + r + dx), channels 4g .. 4g + 3
-                        const v4s a = tl[((ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
-                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[dy * 3 + dx], a, acc, 0, 0, 0);
-                    }
+                win.apply(tl, (ry * TROW + 16 * wave + r) * 4, acc);
                 const int y = y0 + ry, xv = xs + r;
                 if (xv < A.X) conv_store<EPI_RELU>(A, acc, bias, (n * A.Y + y) * A.X + xv, 0, g);
             }
@@ -483,10 +510,11 @@ __global__ __launch_bounds__(256) void k_conv3d(const ConvArgs A)
     // ring slot of slice z (z >= zbeg - 1)
     auto slot = [&](int z) { return (z - zbeg + 1) % 3; };
     __syncthreads();                         // the weights are staged
-    // this lane's weight blocks stay in registers (LDS then serves only the activations)
-    v4s wr[TAPS];
+    // this lane's weight blocks stay in registers (LDS then serves only the activations):
+    // per depth tap dz a 3x3 window of two taps per MFMA (five per window)
+    Window<2> win[3];
 #pragma unroll
-    for (int q = 0; q < TAPS; ++q) wr[q] = wl[q * (CH * 4) + r * 4 + g];
+    for (int dz = 0; dz < 3; ++dz) win[dz].load(wl, dz * 9, r, g);
     uint4 reg[SL_LD];
     slice_fetch(A, n, zbeg - 1, y0, x0, reg);
 #pragma unroll
@@ -515,16 +543,8 @@ __global__ __launch_bounds__(256) void k_conv3d(const ConvArgs A)
         for (int ry = 0; ry < TY3 && y0 + ry < A.Y; ++ry) {
             v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int dz = 0; dz < 3; ++dz) {
-                const int sb = slot(z - 1 + dz) * SL_VOX;
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) {
-                        const v4s a = tl[(sb + (ry + dy) * TROW + 16 * wave + r + dx) * 4 + g];
-                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[(dz * 3 + dy) * 3 + dx], a, acc, 0, 0, 0);
-                    }
-            }
+            for (int dz = 0; dz < 3; ++dz)
+                win[dz].apply(tl, (slot(z - 1 + dz) * SL_VOX + ry * TROW + 16 * wave + r) * 4, acc);
             const int y = y0 + ry, xv = xs + r;
             if (xv < A.X) {
                 const int64_t row = ((int64_t)n * A.Z + z) * A.Y + y;
@@ -542,12 +562,13 @@ struct WgradArgs {
     float *part;            // [n_waves][PART]
 };
 
-// dW[tap][o][i] = sum_p g[p][o] h[p + tap - 1][i]: M = o, N = i, K = voxels.
+// dW[tap][o][i] = sum_p g[p][o] h[p + tap - 1][i]: M = o, N = i, K = voxels,
+// 32 voxels of one x row per MFMA (lane group g takes voxels 8g .. 8g + 7).
 __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs A)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
-    const int nsx = (A.X + 15) / 16;
+    const int nsx = (A.X + 31) / 32;
     const int64_t nseg = (int64_t)A.N * A.Z * A.Y * nsx;
     v4f acc[TAPS];
 #pragma unroll
@@ -559,12 +580,12 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs A)
         const int y = (int)(t % A.Y); t /= A.Y;
         const int z = (int)(t % A.Z);
         const int n = (int)(t / A.Z);
-        const int x0 = xs * 16;
+        const int x0 = xs * 32;
         const int64_t vrow = (((int64_t)n * A.Z + z) * A.Y + y) * A.X;
-        v4s ga;
+        v8s ga;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int xv = x0 + 4 * g + j;
+        for (int j = 0; j < 8; ++j) {
+            const int xv = x0 + 8 * g + j;
             const uint16_t gv = xv < A.X ? A.g[(vrow + xv) * CH + r] : (uint16_t)0;
             ga[j] = (short)gv;
             bsum += bf2f(gv);
@@ -580,15 +601,16 @@ __global__ __launch_bounds__(256) void k_wgrad(const WgradArgs A)
                 const int64_t row = (((int64_t)n * A.Z + zz) * A.Y + yy) * A.X;
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
-                    v4s hb;
+                    v8s hb;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int xv = x0 + 4 * g + j;
+                    for (int j = 0; j < 8; ++j) {
+                        const int xv = x0 + 8 * g + j;
                         const int xx = xv + dx - 1;
                         hb[j] = (short)((xv < A.X && xx >= 0 && xx < A.X) ? A.h[(row + xx) * CH + r] : (uint16_t)0);
                     }
                     const int tap = (dz * 3 + dy) * 3 + dx;
-                    acc[tap] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ga, hb, acc[tap], 0, 0, 0);
+                    acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, ga),
+                                                                       __builtin_bit_cast(v8bf, hb), acc[tap], 0, 0, 0);
                 }
             }
         }
