@@ -150,6 +150,10 @@ CONFIGS = {
                   weights="paper"),
     "c2sp": Config(32, (48, 48, 40), 6, (72, 64), "interlaced", 16, 360.0, *_ratio_geom(48), 6, tol=1e-6,
                    weights="paper"),
+    # odd sizes everywhere (voxel planes at half-integers, a voxel straddling z = 0, the detector
+    # centre between pixels) and a detector shifted off the central ray
+    "odd": Config(18, (21, 17, 23), 3, (33, 29), "golden", 7, 180.0, *_ratio_geom(21), 3, tol=1e-6,
+                  extra={"det_off": (0.37, -0.61)}),
     # tall volumes (nz > 128): several z voxels per lane in the voxel-driven adjoint
     "tall3": Config(16, (20, 18, 150), 2, (32, 164), "golden", 6, 180.0, 1000.0, 2000.0, 3, tol=1e-6),
     "tall4": Config(17, (16, 14, 230), 2, (28, 244), "interlaced", 5, 360.0, 1000.0, 2000.0, 3, tol=1e-6),
@@ -204,8 +208,9 @@ def make_geometry(cfg: Config, n_frames: int | None = None) -> Geometry:
     off = np.zeros(nf + 1, dtype=np.int64)
     off[1:] = np.cumsum(counts)
     nx, ny, nz = cfg.n
+    ou, ov = cfg.extra.get("det_off", (0.0, 0.0))
     return Geometry(nx, ny, nz, nf, cfg.det[0], cfg.det[1], cfg.du, cfg.du, cfg.src_iso, cfg.src_det,
-                    off, ang)
+                    off, ang, ou, ov)
 
 
 # ---------------------------------------------------------------------------

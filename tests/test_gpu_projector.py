@@ -1,4 +1,7 @@
-"""GPU parity of the HIP projector A and backprojector A^T against the FP64 oracle."""
+"""GPU parity of the HIP projector A and backprojector A^T against the FP64 oracle.
+
+The `odd` workload has odd sizes everywhere (voxel planes at half-integers, a voxel straddling
+z = 0, the detector centre between pixels) and a detector shifted off the central ray."""
 import numpy as np
 import pytest
 
@@ -32,7 +35,7 @@ def _frame_rel(g, got, want):
     return max(errs)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s", "tall4"])
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s", "tall4", "odd"])
 def test_project_matches_oracle(msf, name):
     cfg, g, x0, v, y, lam = problem(name)
     print("case", name, flush=True)
@@ -46,7 +49,7 @@ def test_project_matches_oracle(msf, name):
 
 @pytest.mark.parametrize("name,back", [("c1", 2), ("c3s", 2), ("c5s", 2), ("c1", 1), ("c3s", 1), ("c5s", 1), ("c1", 0),
                                        ("c3s", 0), ("tall3", 2), ("tall3", 1), ("tall4", 2), ("tall4", 1),
-                                       ("tall4", 0)])
+                                       ("tall4", 0), ("odd", 2), ("odd", 1), ("odd", 0)])
 def test_backproject_matches_oracle(msf, name, back):
     """Every adjoint: voxel-driven gather from the cell table (2, default) or on the fly (1),
     and the ray-driven scatter (0)."""
@@ -60,7 +63,8 @@ def test_backproject_matches_oracle(msf, name, back):
         assert rel_l2(got[f], want[f]) <= 2e-6
 
 
-@pytest.mark.parametrize("name,back", [("c1", 2), ("c2s", 2), ("c3s", 2), ("c1", 1), ("c2s", 1), ("c3s", 1), ("c2s", 0)])
+@pytest.mark.parametrize("name,back", [("c1", 2), ("c2s", 2), ("c3s", 2), ("c1", 1), ("c2s", 1), ("c3s", 1), ("c2s", 0),
+                                       ("odd", 2), ("odd", 1)])
 def test_dot_product_adjoint(msf, name, back):
     """<A x, y> = <x, A^T y> for the FP32 kernels (products summed in FP64)."""
     cfg, g, *_ = problem(name)
