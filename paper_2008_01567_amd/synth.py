@@ -154,6 +154,9 @@ CONFIGS = {
     # centre between pixels) and a detector shifted off the central ray
     "odd": Config(18, (21, 17, 23), 3, (33, 29), "golden", 7, 180.0, *_ratio_geom(21), 3, tol=1e-6,
                   extra={"det_off": (0.37, -0.61)}),
+    # an odd number of detector rows and no offset: the middle row is level (zp = 0) and, nz being
+    # even, runs in the face z = 0 between two voxel slabs (the upper one takes it, half-open voxels)
+    "level": Config(19, (24, 20, 16), 2, (31, 31), "golden", 6, 180.0, *_ratio_geom(24), 3, tol=1e-6),
     # tall volumes (nz > 128): several z voxels per lane in the voxel-driven adjoint
     "tall3": Config(16, (20, 18, 150), 2, (32, 164), "golden", 6, 180.0, 1000.0, 2000.0, 3, tol=1e-6),
     "tall4": Config(17, (16, 14, 230), 2, (28, 244), "interlaced", 5, 360.0, 1000.0, 2000.0, 3, tol=1e-6),

@@ -1,7 +1,8 @@
 """GPU parity of the HIP projector A and backprojector A^T against the FP64 oracle.
 
 The `odd` workload has odd sizes everywhere (voxel planes at half-integers, a voxel straddling
-z = 0, the detector centre between pixels) and a detector shifted off the central ray."""
+z = 0, the detector centre between pixels) and a detector shifted off the central ray; `level` has a
+level middle row (zp = 0) that runs in the voxel face z = 0."""
 import numpy as np
 import pytest
 
@@ -35,7 +36,7 @@ def _frame_rel(g, got, want):
     return max(errs)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s", "tall4", "odd"])
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s", "tall4", "odd", "level"])
 def test_project_matches_oracle(msf, name):
     cfg, g, x0, v, y, lam = problem(name)
     print("case", name, flush=True)
@@ -43,13 +44,20 @@ def test_project_matches_oracle(msf, name):
     want = oracle.project(g, x0)
     got = plan.project(_dev(x0)).cpu().numpy()
     assert _frame_rel(g, got, want) <= 2e-6
-    # rows that miss the volume are exactly zero
-    assert np.all(got[want == 0.0] == 0.0)
+    # rows whose ray misses the volume (an empty row of A: zero chord through the box) are
+    # exactly zero.  (A ray through a zero-valued region is not such a row: where its xy line
+    # runs through a corner shared by four cells, as the central column's does through the
+    # rotation axis, the FP32 piece ends near s = 0 can leave a piece of ~1e-16 in a cell the
+    # exact line only touches.)
+    miss = oracle.project(g, np.ones_like(x0)) == 0.0
+    assert miss.any()
+    assert np.all(got[miss] == 0.0)
 
 
 @pytest.mark.parametrize("name,back", [("c1", 2), ("c3s", 2), ("c5s", 2), ("c1", 1), ("c3s", 1), ("c5s", 1), ("c1", 0),
                                        ("c3s", 0), ("tall3", 2), ("tall3", 1), ("tall4", 2), ("tall4", 1),
-                                       ("tall4", 0), ("odd", 2), ("odd", 1), ("odd", 0)])
+                                       ("tall4", 0), ("odd", 2), ("odd", 1), ("odd", 0), ("level", 2),
+                                       ("level", 1), ("level", 0)])
 def test_backproject_matches_oracle(msf, name, back):
     """Every adjoint: voxel-driven gather from the cell table (2, default) or on the fly (1),
     and the ray-driven scatter (0)."""
@@ -64,7 +72,7 @@ def test_backproject_matches_oracle(msf, name, back):
 
 
 @pytest.mark.parametrize("name,back", [("c1", 2), ("c2s", 2), ("c3s", 2), ("c1", 1), ("c2s", 1), ("c3s", 1), ("c2s", 0),
-                                       ("odd", 2), ("odd", 1)])
+                                       ("odd", 2), ("odd", 1), ("level", 2), ("level", 1)])
 def test_dot_product_adjoint(msf, name, back):
     """<A x, y> = <x, A^T y> for the FP32 kernels (products summed in FP64)."""
     cfg, g, *_ = problem(name)
