@@ -88,6 +88,7 @@ void row_range(msf_plan &P)
 // the volume, in as few 64-row passes as possible.
 int default_rays_per_lane(const msf_plan &P)
 {
+    if (P.steep) return 1;   // the general z walk runs one ray per lane
     const int rows = P.iv_hi - P.iv_lo + 1;
     const int need = (rows + 63) / 64;
     if (need <= 4) return std::max(need, 1);
@@ -144,6 +145,9 @@ msf_status ensure_cell_table(msf_plan &P)
 
 msf_status setup_tiles(msf_plan &P)
 {
+    // where a ray can cross two z planes inside one xy cell the projector runs the
+    // general z walk, compiled for one ray per lane only: the tiles follow it
+    if (P.steep) P.tiles.rays_per_lane = 1;
     if (P.tiles.back_mode == 2) {
         const msf_status st = ensure_cell_table(P);
         if (st != MSF_OK) return st;
@@ -455,6 +459,7 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
         for (int w : W)
             for (int r : R) {
                 if (r > std::max(need, 1) + 1) continue;   // more rays per lane than rows: idle lanes
+                if (P->steep && r != 1) continue;          // steep plans run one ray per lane
                 msf_tiles t{r, w, 1, xr};
                 P->tiles = t;
                 if (setup_tiles(*P) != MSF_OK) continue;

@@ -193,6 +193,7 @@ class Plan:
             pass
 
     def set_tiles(self, rays_per_lane=3, waves_per_group=4, back_mode=2, xcd_remap=1):
+        """Set the launch shapes (msf_plan_set_tiles); get_tiles() reads back what the plan keeps."""
         t = msf_tiles(rays_per_lane, waves_per_group, back_mode, xcd_remap)
         _check(lib().msf_plan_set_tiles(self._h, C.byref(t)))
 

@@ -157,6 +157,15 @@ CONFIGS = {
     # an odd number of detector rows and no offset: the middle row is level (zp = 0) and, nz being
     # even, runs in the face z = 0 between two voxel slabs (the upper one takes it, half-open voxels)
     "level": Config(19, (24, 20, 16), 2, (31, 31), "golden", 6, 180.0, *_ratio_geom(24), 3, tol=1e-6),
+    # a source close to a tall volume: rays climb up to ~2 (steep) and ~3 (steeper) voxels in z per
+    # voxel of xy path, so one ray crosses several z planes inside one xy cell; steeper's cells
+    # also meet more than three detector columns
+    "steep": Config(24, (16, 16, 48), 3, (48, 96), "golden", 6, 180.0, 28.0, 56.0, 3, tol=1e-6),
+    "steeper": Config(25, (16, 16, 48), 2, (48, 112), "golden", 6, 180.0, 20.0, 40.0, 3, tol=1e-6),
+    # a single voxel slab (nz = 1); the shifted rows put one ray (zp = -1) through the slab's lower
+    # face near the isocentre and one (zp = 0.2) inside the slab all the way
+    "flat": Config(26, (24, 20, 1), 3, (64, 8), "golden", 7, 180.0, 200.0, 400.0, 2, pitch_at_iso=0.6,
+                   tol=1e-6, extra={"det_off": (0.0, -0.4)}),
     # tall volumes (nz > 128): several z voxels per lane in the voxel-driven adjoint
     "tall3": Config(16, (20, 18, 150), 2, (32, 164), "golden", 6, 180.0, 1000.0, 2000.0, 3, tol=1e-6),
     "tall4": Config(17, (16, 14, 230), 2, (28, 244), "interlaced", 5, 360.0, 1000.0, 2000.0, 3, tol=1e-6),

@@ -2,7 +2,9 @@
 
 The `odd` workload has odd sizes everywhere (voxel planes at half-integers, a voxel straddling
 z = 0, the detector centre between pixels) and a detector shifted off the central ray; `level` has a
-level middle row (zp = 0) that runs in the voxel face z = 0."""
+level middle row (zp = 0) that runs in the voxel face z = 0.  `steep` and `steeper` put the source
+close to a tall volume, so that rays cross several z planes inside one xy cell; `flat` is a single
+voxel slab."""
 import numpy as np
 import pytest
 
@@ -168,3 +170,45 @@ def test_fine_detector_rows(msf, pitch, det, back):
     got_b = plan.backproject(_dev(yy)).cpu().numpy()
     for f in range(g.n_frames):
         assert rel_l2(got_b[f], want_b[f]) <= 2e-6
+
+
+@pytest.mark.parametrize("name,back", [("steep", 2), ("steep", 1), ("steep", 0), ("steeper", 1), ("steeper", 0),
+                                       ("flat", 2), ("flat", 1), ("flat", 0)])
+def test_degenerate_geometries(msf, name, back):
+    """Steep rays (the forward projector and the scatter adjoint take their general z walk,
+    which runs one ray per lane, and the gathers read rows past their two candidates) and a
+    one-voxel slab: A and A^T of random volumes and sinograms against the oracle, exact zeros
+    on rows that miss the volume, and the tile shape the plan keeps.  On `steeper` more than
+    three detector columns meet a cell, so there is no cell table (back_mode 2)."""
+    print("case", name, back, flush=True)
+    cfg = synth.config(name)
+    g = synth.make_geometry(cfg)
+    nx, ny, nz = cfg.n
+    steep = name.startswith("steep")
+    plan = msf.Plan(g)
+    if steep:
+        assert plan.get_tiles()["rays_per_lane"] == 1   # 96 and 112 rows would ask for 2
+    if name == "steeper":
+        assert plan.get_tiles()["back_mode"] == 1
+        with pytest.raises(msf.MsfError):
+            plan.set_tiles(back_mode=2)
+    plan.set_tiles(rays_per_lane=3, back_mode=back)
+    tiles = plan.get_tiles()
+    assert tiles["back_mode"] == back
+    assert tiles["rays_per_lane"] == (1 if steep else 3)
+    rng = np.random.default_rng(1000 * cfg.cid + 91)
+    x = rng.uniform(0.5, 1.5, size=(g.n_frames, nz, ny, nx)).astype(np.float32).astype(np.float64)
+    want = oracle.project(g, x)
+    got = plan.project(_dev(x)).cpu().numpy()
+    assert _frame_rel(g, got, want) <= 2e-6
+    miss = want == 0.0   # x > 0 everywhere: exactly the rows with a zero chord through the box
+    assert miss.any() and not miss.all()
+    assert np.all(got[miss] == 0.0)
+    yy = rng.uniform(0.5, 1.5, size=plan.n_meas).astype(np.float32).astype(np.float64)
+    want_b = oracle.backproject(g, yy)
+    got_b = plan.backproject(_dev(yy)).cpu().numpy()
+    for f in range(g.n_frames):
+        assert rel_l2(got_b[f], want_b[f]) <= 2e-6
+    # the pair is adjoint to FP32 rounding: <A x, y> = <x, A^T y>
+    lhs, rhs = float(np.dot(got.reshape(-1), yy)), float(np.dot(x.reshape(-1), got_b.reshape(-1)))
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)

@@ -35,7 +35,8 @@ def _solve(msf, name, **kw):
 # tall volumes (nz 150 and 230) run the adjoint fused with the CG update at 3 and 4 z
 # voxels per lane, the instantiation that the 256^3 and 512x512x256 solves use.
 @pytest.mark.parametrize("name,tol", [("c1", 1e-8), ("c2s", 1e-6), ("c3s", 1e-7), ("tall3", 1e-8),
-                                      ("tall4", 1e-8), ("odd", 1e-8), ("level", 1e-8)])
+                                      ("tall4", 1e-8), ("odd", 1e-8), ("level", 1e-8), ("steep", 1e-8),
+                                      ("steeper", 1e-8), ("flat", 1e-8)])
 def test_prox_matches_oracle(msf, name, tol):
     print("case", name, flush=True)
     cfg, g, x, st = _solve(msf, name, tol=tol, max_iter=5000, true_residual=True)

@@ -236,3 +236,34 @@ def test_rays_missing_volume_are_zero_rows():
     counts = np.diff(M.rowptr).reshape(g.nv, g.nu)
     assert (counts[:, :5] == 0).all() and (counts[:, -5:] == 0).all()
     assert (counts[:, 18:22] > 0).all()
+
+
+@pytest.mark.parametrize("name", ["steep", "steeper", "flat"])
+def test_degenerate_geometries(name):
+    """Rays steep enough to cross two or more z planes inside one xy cell (a source close to a
+    tall volume), and a one-voxel slab: Siddon's rows equal per-voxel clipping and sum to the
+    chord through the volume box; the steep workloads do have such rays."""
+    g = synth.make_geometry(synth.config(name)).subset([0])
+    half = np.array([g.nx, g.ny, g.nz]) / 2.0
+    rng = np.random.default_rng(5)
+    most_in_one_cell = 0
+    hits = 0
+    for _ in range(300):
+        view, iu, iv = int(rng.integers(len(g.angles))), int(rng.integers(g.nu)), int(rng.integers(g.nv))
+        S, D = oracle.ray(g, g.angles[view], iu, iv)
+        a = _entries_dict(*oracle.ray_entries(g, S, D, "siddon"), 1e-13)
+        b = _entries_dict(*oracle.ray_entries(g, S, D, "brute"), 1e-13)
+        assert a.keys() == b.keys()
+        for k in a:
+            assert abs(a[k] - b[k]) <= 1e-13
+        assert abs(sum(a.values()) - _box_chord(S, D, -half, half)) <= 1e-11
+        hits += bool(a)
+        cells = {}
+        for k in a:   # voxel index (iz * ny + iy) * nx + ix
+            cells[k % (g.nx * g.ny)] = cells.get(k % (g.nx * g.ny), 0) + 1
+        most_in_one_cell = max([most_in_one_cell] + list(cells.values()))
+    assert hits >= 30
+    if name == "flat":
+        assert most_in_one_cell == 1
+    else:
+        assert most_in_one_cell >= 3
