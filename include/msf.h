@@ -84,7 +84,7 @@ typedef struct msf_cnn msf_cnn;
 
 /* Kernel launch shapes (chosen by the autotuner, or defaults). */
 typedef struct msf_tiles {
-    int32_t rays_per_lane;       /* rays of one detector column per lane: 1, 2, 3, 4 or 6.  A geometry where a
+    int32_t rays_per_lane;       /* rays of one detector column per lane: 1 to 6.  A geometry where a
                                     ray can cross two z planes inside one xy cell (rays steeper than 45 degrees
                                     over a cell diagonal) always runs 1: the plan stores 1 whatever is asked */
     int32_t waves_per_group;     /* projector workgroup size in 64-lane waves: 1, 2 or 4 */

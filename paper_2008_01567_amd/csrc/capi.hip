@@ -91,8 +91,7 @@ int default_rays_per_lane(const msf_plan &P)
     if (P.steep) return 1;   // the general z walk runs one ray per lane
     const int rows = P.iv_hi - P.iv_lo + 1;
     const int need = (rows + 63) / 64;
-    if (need <= 4) return std::max(need, 1);
-    return 6;
+    return std::min(std::max(need, 1), 6);
 }
 
 // Per (view, xy cell) piece table of the table-driven voxel adjoint, built once
@@ -186,8 +185,7 @@ msf_status setup_tiles(msf_plan &P)
 
 bool tiles_ok(const msf_tiles &t)
 {
-    return (t.rays_per_lane == 1 || t.rays_per_lane == 2 || t.rays_per_lane == 3 || t.rays_per_lane == 4 ||
-            t.rays_per_lane == 6) &&
+    return (t.rays_per_lane >= 1 && t.rays_per_lane <= 6) &&
            (t.waves_per_group == 1 || t.waves_per_group == 2 || t.waves_per_group == 4) &&
            (t.back_mode >= 0 && t.back_mode <= 2) && (t.xcd_remap == 0 || t.xcd_remap == 1);
 }
@@ -452,7 +450,7 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
     msf_tiles best = old;
     float best_t = 1e30f;
     std::vector<std::pair<float, msf_tiles>> cand;   // every timed (forward + voxel-driven adjoint) shape
-    const int R[] = {1, 2, 3, 4, 6}, W[] = {1, 2, 4};
+    const int R[] = {1, 2, 3, 4, 5, 6}, W[] = {1, 2, 4};
     const int need = (P->iv_hi - P->iv_lo + 64) / 64;
     // forward + voxel-driven adjoint over every shape
     for (int xr = 0; xr <= 1; ++xr)

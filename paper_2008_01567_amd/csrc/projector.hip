@@ -1147,6 +1147,7 @@ hipError_t launch_forward(const msf_plan &P, int mode, const float *vol, const f
     case 2: return fwd_dispatch_mode<2, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
     case 3: return fwd_dispatch_mode<3, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
     case 4: return fwd_dispatch_mode<4, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
+    case 5: return fwd_dispatch_mode<5, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
     default: return fwd_dispatch_mode<6, false>(pp, mode, grid, block, vol, P.slam, y, out, P.part_proj, s);
     }
 }
@@ -1166,6 +1167,7 @@ hipError_t launch_back_scatter(const msf_plan &P, const float *sino, double *vol
     case 2: hipLaunchKernelGGL((k_back_scatter<2, false>), grid, block, 0, s, pp, sino, vol_acc); break;
     case 3: hipLaunchKernelGGL((k_back_scatter<3, false>), grid, block, 0, s, pp, sino, vol_acc); break;
     case 4: hipLaunchKernelGGL((k_back_scatter<4, false>), grid, block, 0, s, pp, sino, vol_acc); break;
+    case 5: hipLaunchKernelGGL((k_back_scatter<5, false>), grid, block, 0, s, pp, sino, vol_acc); break;
     default: hipLaunchKernelGGL((k_back_scatter<6, false>), grid, block, 0, s, pp, sino, vol_acc); break;
     }
     return hipGetLastError();

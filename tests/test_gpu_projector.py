@@ -90,7 +90,7 @@ def test_dot_product_adjoint(msf, name, back):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
-@pytest.mark.parametrize("rpl,wpg,xcd", [(1, 1, 0), (1, 4, 1), (2, 2, 1), (3, 4, 1), (4, 4, 0), (6, 1, 1)])
+@pytest.mark.parametrize("rpl,wpg,xcd", [(1, 1, 0), (1, 4, 1), (2, 2, 1), (3, 4, 1), (4, 4, 0), (5, 2, 0), (6, 1, 1)])
 def test_tile_shapes_give_same_results(msf, rpl, wpg, xcd):
     """Launch shapes change only the mapping of work: the forward projection is
     bit-identical; both gather adjoints are bit-identical too (the same pieces, in
