@@ -162,7 +162,8 @@ msf_status msf_plan_get_tiles(const msf_plan *plan, msf_tiles *tiles);
  * the fastest (forward + adjoint) pair.
  * cache_path (may be NULL): text file of "key tiles" lines, key = GPU arch +
  * geometry sizes + a hash of the angle list; a hit is applied without timing,
- * a miss is appended.  chosen (host, may be NULL) receives the shape. */
+ * a miss is appended.  chosen (host, may be NULL) receives the shape the plan
+ * keeps (on a steep geometry with one ray per lane, see msf_tiles). */
 msf_status msf_plan_autotune(msf_plan *plan, const char *cache_path, msf_tiles *chosen, void *stream);
 
 /* Per-plan sizes (host outputs, any may be NULL). */

@@ -421,7 +421,7 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
                            &t.xcd_remap) == 4 && tiles_ok(t)) {
                     fclose(f);
                     msf_status st = msf_plan_set_tiles(P, &t);
-                    if (st == MSF_OK && chosen) *chosen = t;
+                    if (st == MSF_OK && chosen) *chosen = P->tiles;   // as the plan keeps it
                     return st;
                 }
             }
@@ -502,7 +502,7 @@ msf_status msf_plan_autotune(msf_plan *P, const char *cache_path, msf_tiles *cho
     msf_status st = setup_tiles(*P);
     if (st != MSF_OK) return st;
     HIPCHK(hipStreamSynchronize(s));
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = P->tiles;
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "a")) {
             fprintf(f, "%s %d %d %d %d\n", key, best.rays_per_lane, best.waves_per_group, best.back_mode, best.xcd_remap);
