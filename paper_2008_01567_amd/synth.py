@@ -169,6 +169,9 @@ CONFIGS = {
     # tall volumes (nz > 128): several z voxels per lane in the voxel-driven adjoint
     "tall3": Config(16, (20, 18, 150), 2, (32, 164), "golden", 6, 180.0, 1000.0, 2000.0, 3, tol=1e-6),
     "tall4": Config(17, (16, 14, 230), 2, (28, 244), "interlaced", 5, 360.0, 1000.0, 2000.0, 3, tol=1e-6),
+    # taller than one gather wave's 256 voxels (two z-chunks per voxel column), and about 300 detector
+    # rows meeting the volume (five rays per lane by default)
+    "tall5": Config(27, (12, 10, 300), 2, (20, 316), "golden", 5, 180.0, 1000.0, 2000.0, 3, tol=1e-6),
 }
 
 

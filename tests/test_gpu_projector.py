@@ -4,7 +4,7 @@ The `odd` workload has odd sizes everywhere (voxel planes at half-integers, a vo
 z = 0, the detector centre between pixels) and a detector shifted off the central ray; `level` has a
 level middle row (zp = 0) that runs in the voxel face z = 0.  `steep` and `steeper` put the source
 close to a tall volume, so that rays cross several z planes inside one xy cell; `flat` is a single
-voxel slab."""
+voxel slab; `tall5` (nz 300) splits each voxel column of the gather into two z-chunks."""
 import numpy as np
 import pytest
 
@@ -38,11 +38,13 @@ def _frame_rel(g, got, want):
     return max(errs)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s", "tall4", "odd", "level"])
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s", "tall4", "tall5", "odd", "level"])
 def test_project_matches_oracle(msf, name):
     cfg, g, x0, v, y, lam = problem(name)
     print("case", name, flush=True)
     plan = msf.Plan(g)
+    if name == "tall5":   # 304 rows meet the volume: one chunk of five rays per lane
+        assert plan.get_tiles()["rays_per_lane"] == 5
     want = oracle.project(g, x0)
     got = plan.project(_dev(x0)).cpu().numpy()
     assert _frame_rel(g, got, want) <= 2e-6
@@ -58,8 +60,8 @@ def test_project_matches_oracle(msf, name):
 
 @pytest.mark.parametrize("name,back", [("c1", 2), ("c3s", 2), ("c5s", 2), ("c1", 1), ("c3s", 1), ("c5s", 1), ("c1", 0),
                                        ("c3s", 0), ("tall3", 2), ("tall3", 1), ("tall4", 2), ("tall4", 1),
-                                       ("tall4", 0), ("odd", 2), ("odd", 1), ("odd", 0), ("level", 2),
-                                       ("level", 1), ("level", 0)])
+                                       ("tall4", 0), ("tall5", 2), ("tall5", 1), ("tall5", 0), ("odd", 2),
+                                       ("odd", 1), ("odd", 0), ("level", 2), ("level", 1), ("level", 0)])
 def test_backproject_matches_oracle(msf, name, back):
     """Every adjoint: voxel-driven gather from the cell table (2, default) or on the fly (1),
     and the ray-driven scatter (0)."""
