@@ -43,7 +43,7 @@ VALU_OPS_PER_INTERSECTION = 12
 # kernel of known size in the same run (read x2.0, write x1.0).  Valid only
 # for the projector source and launch shape they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "ba5975e86a67b8130d45ab9984c253b298dca72ddcbc3ac8d52b79a2a43b09cb",
+    "source_sha256": "10307d56b95a222f3ebffc2720159b99b5d3def4f60e0e1696eb875fa9c71261",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
     "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.4e6,
     "read_bytes": 987.4e6, "write_bytes": 265.0e6, "l2_hit_rate": 0.933,

@@ -472,8 +472,13 @@ __global__ void k_walk_table(const ProjParams P, int64_t n_cols, WalkHead *__res
     head[i] = h;
 }
 
+// Five rays per lane from the walk table fit in 96 registers without spilling,
+// which runs 5 waves per SIMD instead of the 4 that 110 registers allow
+// (256^3 x 24: 7.33 -> 7.13 ms per projection).  Six would spill.
 template <int R, int MODE, bool STEEP, bool WT>
-__global__ __launch_bounds__(256) void k_forward(const ProjParams P, const float *__restrict__ vol,
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((R == 5 && WT && (MODE == PM_PLAIN || MODE == PM_WEIGHTED)) ? 5 : 1)))
+void k_forward(const ProjParams P, const float *__restrict__ vol,
                                                  const float *__restrict__ lam, const float *__restrict__ y,
                                                  float *__restrict__ out, double *__restrict__ partial)
 {
