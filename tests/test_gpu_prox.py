@@ -98,12 +98,40 @@ def test_paper_weight_model_reaches_the_fp32_floor(msf):
 
 
 def test_graph_equals_eager(msf):
-    """The same 300 CG steps replayed from captured graphs and launched eagerly
-    (results differ only by the order of the FP64 atomic adds)."""
+    """The same 300 CG steps replayed from captured graphs and launched eagerly."""
     cfg, g, xa, sa = _solve(msf, "c2s", tol=0.0, max_iter=300, check_every=16, use_graph=True)
     _, _, xb, sb = _solve(msf, "c2s", tol=0.0, max_iter=300, check_every=16, use_graph=False)
     assert (sa["iters"] == 300).all() and (sb["iters"] == 300).all()
     assert rel_l2(xa, xb) <= 1e-5
+
+
+def test_repeated_solves_replay_the_graph(msf):
+    """A plan captures its CG steps once and replays the graph in later solves: three solves on
+    one plan (inputs a, b, a, with other device work and synchronisations between them) equal
+    fresh plans' solves bit for bit, iteration counts included."""
+    cfg, g, x0, v, y, lam = problem("c2s")
+    rng = np.random.default_rng(2024)
+    v2 = (v + 0.01 * rng.standard_normal(v.shape)).astype(np.float32).astype(np.float64)
+    y2 = (y * (1.0 + 0.01 * rng.standard_normal(y.shape))).astype(np.float32).astype(np.float64)
+
+    def solve(plan, vv, yy):
+        x, st = plan.prox_solve(_dev(vv), _dev(yy), _dev(lam), cfg.sigma, tol=1e-6, max_iter=3000, check_every=8)
+        return x.cpu().numpy(), st["iters"].copy()
+
+    want = {}
+    for key, vv, yy in (("a", v, y), ("b", v2, y2)):
+        fresh = msf.Plan(g)
+        want[key] = solve(fresh, vv, yy)
+        fresh.close()
+    assert not np.array_equal(want["a"][0], want["b"][0])
+    plan = msf.Plan(g)
+    for key, vv, yy in (("a", v, y), ("b", v2, y2), ("a", v, y)):
+        junk = torch.randn(1 << 20, device="cuda")
+        junk.mul_(2.0).sum().item()   # eager work between the solves
+        x, iters = solve(plan, vv, yy)
+        print(key, "iters", iters.tolist(), flush=True)
+        assert np.array_equal(iters, want[key][1])
+        assert np.array_equal(x, want[key][0])
 
 
 def test_table_and_on_the_fly_gather_give_identical_solves(msf):
