@@ -904,6 +904,22 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
         L.zneg[k] = fminf(zlo[k], 0.0f);
         acc[k] = 0.0;
     }
+    // FUSED: the CG update's p, x and r of the lane's voxels are loaded before
+    // the views, so that their latency hides behind the gather instead of
+    // ending every wave (128^3 x 16: 778 -> 744 us; 512 x 512 x 256: 55.1 ->
+    // 53.6 ms, despite 4 waves per SIMD instead of 5 at 4 voxels per lane).
+    // Only this lane writes these voxels, and only after the views.
+    float pre_p[ZPL], pre_x[ZPL], pre_r[ZPL];
+    if constexpr (FUSED) {
+        const int64_t col0 = (int64_t)f * P.nvox + (int64_t)(iy * P.nx + (col_ok ? ix : 0)) * P.nz;
+#pragma unroll
+        for (int k = 0; k < ZPL; ++k) {
+            const int64_t i0 = col0 + (col_ok && iz[k] < P.nz ? iz[k] : 0);
+            pre_p[k] = U.p[i0];
+            pre_x[k] = U.x[i0];
+            pre_r[k] = U.r[i0];
+        }
+    }
     // detector row coordinate at z = 0 (row = z * rows-per-z + c), widened by 1e-3 row
     const float c_lo = (float)(0.5 * (P.nv - 1) - P.offv / P.dv) - 1e-3f;
     // views of the frame (fewer than 2^31 in all)
@@ -1057,10 +1073,10 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
     for (int k = 0; k < ZPL; ++k) {
         if (col_ok && iz[k] < P.nz) {
             const int64_t i = col + iz[k];
-            const double pv = U.p[i];
+            const double pv = pre_p[k];
             const double q = acc[k] + pv * is2;
-            U.x[i] = (float)((double)U.x[i] + alpha * pv);
-            const float rf = (float)((double)U.r[i] - alpha * q);
+            U.x[i] = (float)((double)pre_x[k] + alpha * pv);
+            const float rf = (float)((double)pre_r[k] - alpha * q);
             U.r[i] = rf;
             part += (double)rf * (double)rf;
         }
