@@ -43,10 +43,10 @@ VALU_OPS_PER_INTERSECTION = 12
 # kernel of known size in the same run (read x2.0, write x1.0).  Valid only
 # for the projector source and launch shape they were taken on.
 MEASURED_TRAFFIC = {
-    "source_sha256": "5c69f72a7d35295618775b01383b14a10b83f54d5d13a04e66f3d6b426d60fd1",
+    "source_sha256": "61284055c580349d772911a619e07c013a897b30ebb23b51b6eb9b9d1de85100",
     "config": "c2", "tiles": {"rays_per_lane": 3, "waves_per_group": 1, "back_mode": 2, "xcd_remap": 1},
-    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.8e6,
-    "read_bytes": 987.7e6, "write_bytes": 265.1e6, "l2_hit_rate": 0.930,
+    "kernel": "backprojector k_back_gather (cell table)", "bytes_per_launch": 1252.4e6,
+    "read_bytes": 987.3e6, "write_bytes": 265.1e6, "l2_hit_rate": 0.929,
     # SQ_INSTS_VALU x 64 / nnz(A) of the same runs: VALU lane-instructions per intersection
     "valu_lane_instr_per_intersection": 27.1,
     "profile": "profiles/gather_update_c2_128x16_counters.md",

@@ -877,16 +877,19 @@ __global__ __launch_bounds__(256) void k_back_gather(const ProjParams P, const f
     const int nwaves = blockDim.x / WAVE;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int lane = threadIdx.x % WAVE;
-    const int64_t t = logical_tile(blockIdx.x, gridDim.x, P.xcd_remap);
     // the tile decode is wave-uniform: keep its results in scalar registers, so
-    // the table and sinogram addresses derived from them stay scalar too
-    const int f = __builtin_amdgcn_readfirstlane((int)(t / P.g_tiles_per_frame));
-    int64_t local = t - (int64_t)f * P.g_tiles_per_frame;
-    const int nxg = (P.nx + nwaves - 1) / nwaves;
+    // the table and sinogram addresses derived from them stay scalar too.  The
+    // launchers keep the grid below 2^31 workgroups, so the decode runs in 32
+    // bits (64-bit divisions cost some 380 scalar instructions of code).
+    const uint32_t t = (uint32_t)logical_tile(blockIdx.x, gridDim.x, P.xcd_remap);
+    const uint32_t tpf = (uint32_t)P.g_tiles_per_frame;
+    const int f = __builtin_amdgcn_readfirstlane((int)(t / tpf));
+    uint32_t local = t - (uint32_t)f * tpf;
+    const uint32_t nxg = (uint32_t)((P.nx + nwaves - 1) / nwaves);
     const int xg = __builtin_amdgcn_readfirstlane((int)(local % nxg));
     local /= nxg;
-    const int iy = __builtin_amdgcn_readfirstlane((int)(local % P.ny));
-    const int zc = __builtin_amdgcn_readfirstlane((int)(local / P.ny));
+    const int iy = __builtin_amdgcn_readfirstlane((int)(local % (uint32_t)P.ny));
+    const int zc = __builtin_amdgcn_readfirstlane((int)(local / (uint32_t)P.ny));
     const int ix = xg * nwaves + wave;
     if (P.active && !P.active[f]) return;   // the whole workgroup belongs to frame f
     const bool col_ok = ix < P.nx;
@@ -1243,6 +1246,7 @@ hipError_t launch_back_gather(const msf_plan &P, const float *sino, double *vol_
     const ProjParams pp = P.proj_params(with_active);
     const int64_t total = pp.g_tiles_per_frame * P.nf;
     if (total == 0) return hipSuccess;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;   // the kernel decodes tiles in 32 bits
     const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
     const GatherUpdate U{};
     return gather_launch<false>(P, pp, grid, block, s, sino, vol_out, U);
@@ -1253,6 +1257,7 @@ hipError_t launch_back_gather_update(const msf_plan &P, hipStream_t s)
     const ProjParams pp = P.proj_params(true);
     const int64_t total = pp.g_tiles_per_frame * P.nf;
     if (total == 0) return hipSuccess;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;   // the kernel decodes tiles in 32 bits
     if (total > P.part_g_per_frame * P.nf) return hipErrorInvalidValue;   // partial buffer sized for other tiles
     const dim3 grid((unsigned)total), block(WAVE * P.tiles.waves_per_group);
     GatherUpdate U;
