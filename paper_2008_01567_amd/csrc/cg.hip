@@ -273,17 +273,32 @@ __global__ __launch_bounds__(VB) void k_update_xr(VolArgs A)
     if (A.active && !A.active[f]) return;
     const double is2 = A.consts[0];
     const double alpha = A.scal[SC_ALPHA * A.nf + f];
-    const int64_t base = (int64_t)f * A.nvox;
-    double s = 0.0;
+    const int64_t base = (int64_t)f * A.nvox + (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
+    const int64_t n = A.nvox - (int64_t)blockIdx.x * VCHUNK - threadIdx.x;   // elements k with k * VB < n
+    // all of the thread's loads first: the stores below could alias them, so the
+    // compiler would otherwise wait for each element's loads after the last store
+    float pl[VE], xl[VE], rl[VE];
+    double bl[VE];
+#pragma unroll
     for (int k = 0; k < VE; ++k) {
-        const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
-        if (i < A.nvox) {
-            const double pv = A.p[base + i];
-            const double q = A.bp[base + i] + pv * is2;
-            A.x[base + i] = (float)((double)A.x[base + i] + alpha * pv);
-            const float rf = (float)((double)A.r[base + i] - alpha * q);
-            A.r[base + i] = rf;
-            A.bp[base + i] = 0.0;
+        const bool in = (int64_t)k * VB < n;
+        const int64_t i = base + (in ? k * VB : 0);
+        pl[k] = A.p[i];
+        xl[k] = A.x[i];
+        rl[k] = A.r[i];
+        bl[k] = A.bp[i];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < VE; ++k) {
+        if ((int64_t)k * VB < n) {
+            const int64_t i = base + k * VB;
+            const double pv = pl[k];
+            const double q = bl[k] + pv * is2;
+            A.x[i] = (float)((double)xl[k] + alpha * pv);
+            const float rf = (float)((double)rl[k] - alpha * q);
+            A.r[i] = rf;
+            A.bp[i] = 0.0;
             s += (double)rf * (double)rf;
         }
     }
@@ -297,13 +312,22 @@ __global__ __launch_bounds__(VB) void k_update_p(VolArgs A)
     const int f = blockIdx.y;
     if (A.active && !A.active[f]) return;
     const double beta = A.scal[SC_BETA * A.nf + f];
-    const int64_t base = (int64_t)f * A.nvox;
-    double s = 0.0;
+    const int64_t base = (int64_t)f * A.nvox + (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
+    const int64_t n = A.nvox - (int64_t)blockIdx.x * VCHUNK - threadIdx.x;   // elements k with k * VB < n
+    // all loads first (see k_update_xr)
+    float rl[VE], pl[VE];
+#pragma unroll
     for (int k = 0; k < VE; ++k) {
-        const int64_t i = (int64_t)blockIdx.x * VCHUNK + k * VB + threadIdx.x;
-        if (i < A.nvox) {
-            const float pf = (float)((double)A.r[base + i] + beta * (double)A.p[base + i]);
-            A.p[base + i] = pf;
+        const int64_t i = base + ((int64_t)k * VB < n ? k * VB : 0);
+        rl[k] = A.r[i];
+        pl[k] = A.p[i];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < VE; ++k) {
+        if ((int64_t)k * VB < n) {
+            const float pf = (float)((double)rl[k] + beta * (double)pl[k]);
+            A.p[base + k * VB] = pf;
             s += (double)pf * (double)pf;
         }
     }
