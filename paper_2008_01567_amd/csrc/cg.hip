@@ -276,13 +276,15 @@ __global__ __launch_bounds__(VB) void k_update_xr(VolArgs A)
     const int64_t base = (int64_t)f * A.nvox + (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
     const int64_t n = A.nvox - (int64_t)blockIdx.x * VCHUNK - threadIdx.x;   // elements k with k * VB < n
     // all of the thread's loads first: the stores below could alias them, so the
-    // compiler would otherwise wait for each element's loads after the last store
+    // compiler would otherwise wait for each element's loads after the last store.
+    // Elements past the frame's end read its first voxel (base itself can be past
+    // the end of the last frame) and are not used.
     float pl[VE], xl[VE], rl[VE];
     double bl[VE];
 #pragma unroll
     for (int k = 0; k < VE; ++k) {
         const bool in = (int64_t)k * VB < n;
-        const int64_t i = base + (in ? k * VB : 0);
+        const int64_t i = in ? base + k * VB : (int64_t)f * A.nvox;
         pl[k] = A.p[i];
         xl[k] = A.x[i];
         rl[k] = A.r[i];
@@ -314,11 +316,11 @@ __global__ __launch_bounds__(VB) void k_update_p(VolArgs A)
     const double beta = A.scal[SC_BETA * A.nf + f];
     const int64_t base = (int64_t)f * A.nvox + (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
     const int64_t n = A.nvox - (int64_t)blockIdx.x * VCHUNK - threadIdx.x;   // elements k with k * VB < n
-    // all loads first (see k_update_xr)
+    // all loads first, elements past the frame's end reading its first voxel (see k_update_xr)
     float rl[VE], pl[VE];
 #pragma unroll
     for (int k = 0; k < VE; ++k) {
-        const int64_t i = base + ((int64_t)k * VB < n ? k * VB : 0);
+        const int64_t i = (int64_t)k * VB < n ? base + k * VB : (int64_t)f * A.nvox;
         rl[k] = A.r[i];
         pl[k] = A.p[i];
     }
