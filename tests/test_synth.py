@@ -59,3 +59,11 @@ def test_measurement_recipe():
     assert np.allclose(yp[:12], yc[:12] + eps[:12] / np.sqrt(lp[:12]))
     # noise of a zero-attenuation ray is s; it grows with attenuation
     assert np.isclose(1 / np.sqrt(np.exp(-0.0) / s0 ** 2), s0)
+
+
+def test_workload_seed_bases_are_distinct():
+    """Every named workload draws from its own seed base (seed = 1000 * cid + stream), so no two
+    workloads share a phantom, noise or view stream by accident."""
+    from collections import Counter
+    counts = Counter(cfg.cid for cfg in synth.CONFIGS.values())
+    assert [cid for cid, n in counts.items() if n > 1] == []
